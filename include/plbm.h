@@ -1,0 +1,191 @@
+/*
+ * plbm.h -- C ABI of libplbm, the MI355X (gfx950) implementation of the
+ * fused collide-and-stream update of the parametric lattice Boltzmann method
+ * (J. W. Shim, "Parametric Lattice Boltzmann Method", arXiv:1402.5487).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns a plbm_status; it never aborts and never throws
+ *    across the ABI.  Arguments are validated on the host before any launch;
+ *    an invalid call launches nothing.
+ *  - "device pointer" arguments are HIP device allocations owned by the caller
+ *    (typically torch tensors); the library never frees them and keeps no
+ *    reference after the call returns.  "host pointer" arguments are ordinary
+ *    host memory owned by the caller.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are asynchronous on that stream unless stated otherwise; a kernel fault
+ *    is reported as PLBM_EHIP by the first later call that synchronises.
+ *  - Velocities are in lattice units (dx = dt = 1) and must be integers for
+ *    streaming.  The 1D rule uses q1d velocities in the paper's order
+ *    (v_1 = 0, v_2,3 = +-a, v_4,5 = +-b, Sec. 2.4); the 2D model is the tensor
+ *    product, population k = i + q1d * j moving with (v_i, v_j).
+ *
+ * Population layout in HBM (structure of arrays, one plane per population)
+ * -------------------------------------------------------------------------
+ *  - dim 2: element (k, y, x) at k * nx * ny + y * nx + x, periodic in x and y.
+ *  - dim 1: element (k, x) at k * (nx + 6) + x + 3: three ghost nodes on each
+ *    side of the nx real nodes (zero-gradient ends, see plbm_step).
+ *  - element type: double (PLBM_F64), float (PLBM_F32), or 16-bit deviations
+ *    (PLBM_F16DEV: IEEE half, PLBM_BF16DEV: bfloat16) decoded as
+ *    f_k = rho0 w_k + scale[k] * h_k with w_k = r_i(0, theta0) r_j(0, theta0).
+ *  - A population buffer holds the POST-collision populations of the last
+ *    completed step; the pre-collision state of Eq. srt at node x is obtained
+ *    by pulling, f_k(x) = buffer_k(x - v_k).  plbm_init writes the buffer
+ *    whose pull is the initial equilibrium.
+ */
+#ifndef PLBM_H
+#define PLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum plbm_status {
+    PLBM_OK = 0,
+    PLBM_EINVAL = -1,        /* bad argument (range, null pointer, size) */
+    PLBM_ESINGULAR = -2,     /* velocity set has duplicates / singular V */
+    PLBM_EHIP = -3,          /* a HIP runtime call failed */
+    PLBM_ENONFINITE = -4,    /* requested invariants are NaN or Inf */
+    PLBM_EUNSUPPORTED = -5   /* valid but not implemented combination */
+} plbm_status;
+
+typedef enum plbm_bc {
+    PLBM_BC_PERIODIC = 0,    /* dim 2 */
+    PLBM_BC_ZEROGRAD = 1     /* dim 1: ghosts copy the edge node */
+} plbm_bc;
+
+typedef enum plbm_storage {
+    PLBM_F64 = 0,
+    PLBM_F32 = 1,
+    PLBM_F16DEV = 2,
+    PLBM_BF16DEV = 3
+} plbm_storage;
+
+#define PLBM_MAX_Q1D 8
+#define PLBM_GHOST 3          /* largest |velocity| the kernels stream */
+
+/* Plain data describing one lattice.  Copied by value into every launch. */
+typedef struct plbm_desc {
+    int32_t dim;              /* 1 or 2 */
+    int32_t nx, ny;           /* ny = 1 when dim = 1 */
+    int32_t q1d;              /* velocities per axis (5 for D1Q5 / D2Q25) */
+    int32_t bc;               /* plbm_bc */
+    int32_t storage;          /* plbm_storage */
+    double v[PLBM_MAX_Q1D];   /* 1D velocities, integers, |v| <= PLBM_GHOST */
+    double c[PLBM_MAX_Q1D * PLBM_MAX_Q1D];  /* c[i*q1d + j], see plbm_coeffs */
+    double omega;             /* relaxation constant, 0 < omega < 2 */
+    double rho0, theta0;      /* deviation base state (16-bit storage only) */
+    float scale[PLBM_MAX_Q1D * PLBM_MAX_Q1D]; /* per-plane scale (16-bit) */
+} plbm_desc;
+
+/*
+ * plbm_coeffs -- coefficient table of the parametric equilibrium.
+ * Sec. 2.1, Eq. rdr: r_i = sum_j c_ij mu_(j-1), with c_ij the coefficient of
+ * degree j-1 of the Lagrange polynomial through (v_k, delta_ik); the Appendix
+ * writes the same table as R = V^-1 M with V[n][k] = v_k^n.  Computed here by
+ * Gaussian elimination with partial pivoting in FP64 on the host, followed by
+ * a residual check of c V = I.
+ *   q : number of velocities, 1..PLBM_MAX_Q1D
+ *   v : host pointer, q velocities (any real values, pairwise distinct)
+ *   c : host pointer, q*q doubles written row-major, c[i*q + j] = c_(i+1)(j+1)
+ * Errors: PLBM_EINVAL (q out of range, null pointer, non-finite v),
+ * PLBM_ESINGULAR (two equal velocities or a residual above 1e-9).
+ * Host only, synchronous, thread-safe.
+ */
+int plbm_coeffs(int q, const double *v, double *c);
+
+/*
+ * plbm_desc_default -- fill *d for the D1Q5 {0, +-1, +-3} model (dim 1) or its
+ * D2Q25 tensor product (dim 2): velocities, c from plbm_coeffs, omega,
+ * boundary (periodic in 2D, zero-gradient in 1D), storage, rho0 = 1,
+ * theta0 = 1/3 and unit scales.  Host only.  PLBM_EINVAL on bad sizes.
+ */
+int plbm_desc_default(plbm_desc *d, int dim, int nx, int ny, double omega,
+                      int storage);
+
+/* Number of stored elements of one population buffer (see layout above),
+ * or 0 if the descriptor is invalid.  Host only. */
+size_t plbm_buffer_elems(const plbm_desc *d);
+
+/* Bytes per stored population (8, 4 or 2), or 0 if invalid.  Host only. */
+size_t plbm_elem_bytes(const plbm_desc *d);
+
+/*
+ * plbm_init -- populations of the initial state f(x, 0) = f_eq(x)
+ * (Eq. eqdist with the tensor-product rule of Eq. rdr), written so that the
+ * first pull of plbm_step or plbm_moments yields exactly that equilibrium.
+ *   rho, ux, uy, theta : device pointers to nx*ny doubles (row-major, x
+ *                        fastest); uy is ignored (may be NULL) when dim = 1.
+ *   f                  : device pointer to plbm_buffer_elems(d) elements.
+ * Asynchronous on `stream`.  Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_EHIP.
+ */
+int plbm_init(const plbm_desc *d, const double *rho, const double *ux,
+              const double *uy, const double *theta, void *f, void *stream);
+
+/*
+ * plbm_step -- nsteps applications of the SRT update, Eq. srt:
+ *   f_i(x + v_i, t + 1) = (1 - omega) f_i(x, t) + omega f_eq_i(x, t),
+ * each one a single fused pull kernel: gather f_k(x) = src_k(x - v_k), take
+ * rho, u, theta, the Maxwell moments mu_0..mu_(q1d-1) per axis, the rule
+ * r = C mu per axis, f_eq = rho r^x r^y, relax, and write dst at x.
+ *   f_a, f_b : device pointers, two distinct buffers of plbm_buffer_elems(d)
+ *              elements.  Step s reads f_a and writes f_b when s is even,
+ *              the reverse when odd: the result is in f_a when nsteps is
+ *              even and in f_b when it is odd.  nsteps >= 0.
+ *   sums     : NULL, or a host pointer to 4 doubles receiving, after the last
+ *              step, the FP64 sums over all nodes of the post-collision
+ *              populations it wrote: sum f, sum f v_x, sum f v_y,
+ *              sum f |v|^2 (mass, momenta, twice the energy).  With periodic
+ *              boundaries these are the invariants of the state after the
+ *              call.  Asking for sums makes the call synchronise `stream`.
+ * Boundaries: dim 2 periodic; dim 1 zero-gradient, i.e. each step the three
+ * ghost nodes at each end receive the post-collision populations of the
+ * nearest real node before streaming.
+ * Errors: PLBM_EINVAL (aliasing or null buffers, bad descriptor),
+ * PLBM_ENONFINITE (sums requested and not finite), PLBM_EHIP.
+ */
+int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
+              double *sums, void *stream);
+
+/*
+ * plbm_moments -- macroscopic fields of the pre-collision state held by f
+ * (pull, then rho = sum f, rho u = sum f v, 2 rho theta = sum f |v - u|^2 in
+ * 2D and rho theta = sum f (v - u)^2 in 1D; one temperature for all axes).
+ *   rho, ux, uy, theta : device pointers to nx*ny doubles, or NULL to skip
+ *                        a field.
+ *   sums               : NULL or a host pointer to 4 doubles: FP64 sums over
+ *                        the nodes of that state (as for plbm_step).
+ *                        Asking for sums synchronises `stream`.
+ * Errors: PLBM_EINVAL, PLBM_ENONFINITE, PLBM_EHIP.
+ */
+int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
+                 double *uy, double *theta, double *sums, void *stream);
+
+/*
+ * plbm_dev_scales -- choose per-plane power-of-two scales for 16-bit
+ * deviation storage from the initial fields: scale[k] = 2^e with e the
+ * smallest integer such that max_x |f_eq_k(x) - rho0 w_k| <= 2^e * 2^10
+ * (FP16: ample headroom below 65504 and well above the subnormal range).
+ * Planes with zero deviation get scale 2^-30.  Writes d->scale.
+ *   rho, ux, uy, theta : device pointers as for plbm_init.
+ * Synchronises `stream`.  Errors: PLBM_EINVAL, PLBM_EHIP.
+ */
+int plbm_dev_scales(plbm_desc *d, const double *rho, const double *ux,
+                    const double *uy, const double *theta, void *stream);
+
+/* Static description of a status code. */
+const char *plbm_strerror(int status);
+
+/* Text of the last HIP runtime error that made a call on this thread return
+ * PLBM_EHIP ("" if none).  Owned by the library; valid until the next call
+ * on the same thread. */
+const char *plbm_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLBM_H */

@@ -38,8 +38,14 @@ def _load():
     lib.ref_step.argtypes = [i, i, i, i, _D, _D, d, i, _D, i, i]
     lib.ref_moments.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, i]
     lib.ref_sums.argtypes = [i, i, i, i, _D, _D, _D]
+    lib.ref_num_threads.argtypes = []
     _lib = lib
     return lib
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().ref_num_threads())
 
 
 def _p(a):

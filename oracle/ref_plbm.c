@@ -40,6 +40,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define REF_MAXQ 8
 #define REF_GHOST 3
@@ -337,4 +340,14 @@ int ref_sums(int dim, int nx, int ny, int q1d, const double *vel,
     }
     for (int m = 0; m < 4; ++m) out[m] = s[m] + comp[m];
     return 0;
+}
+
+/* Threads the parallel loops above run on (1 without OpenMP). */
+int ref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,160 @@
+"""ctypes binding of libplbm (include/plbm.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts Python
+arguments into the C ABI and raises PlbmError on a non-zero status.  If the
+shared library has not been built, importing this module fails loudly.
+"""
+import ctypes
+import os
+
+# libplbm must share torch's HIP runtime (torch owns the device memory and the
+# streams it is handed).  Importing torch first loads torch's libamdhip64, so
+# the library's dependency on that soname resolves to the same copy instead of
+# pulling a second runtime into the process.
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libplbm.so")
+
+PLBM_OK = 0
+PLBM_EINVAL = -1
+PLBM_ESINGULAR = -2
+PLBM_EHIP = -3
+PLBM_ENONFINITE = -4
+PLBM_EUNSUPPORTED = -5
+
+PLBM_BC_PERIODIC = 0
+PLBM_BC_ZEROGRAD = 1
+
+PLBM_F64, PLBM_F32, PLBM_F16DEV, PLBM_BF16DEV = 0, 1, 2, 3
+STORAGE = {"f64": PLBM_F64, "f32": PLBM_F32, "f16dev": PLBM_F16DEV,
+           "bf16dev": PLBM_BF16DEV}
+
+MAX_Q1D = 8
+GHOST = 3
+
+
+class PlbmDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("q1d", ctypes.c_int32),
+        ("bc", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("v", ctypes.c_double * MAX_Q1D),
+        ("c", ctypes.c_double * (MAX_Q1D * MAX_Q1D)),
+        ("omega", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("theta0", ctypes.c_double),
+        ("scale", ctypes.c_float * (MAX_Q1D * MAX_Q1D)),
+    ]
+
+
+class PlbmError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        msg = f"{what}: {strerror(status)} ({status})"
+        if status == PLBM_EHIP:
+            msg += ": " + lib.plbm_last_hip_error().decode()
+        super().__init__(msg)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libplbm.so is not built ({LIB_PATH}); run "
+            "`python -c 'import __graft_entry__ as g; g.build()'` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    D = ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER(PlbmDesc)
+    vp = ctypes.c_void_p
+    lib.plbm_coeffs.argtypes = [ctypes.c_int, D, D]
+    lib.plbm_desc_default.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_int]
+    lib.plbm_buffer_elems.argtypes = [P]
+    lib.plbm_buffer_elems.restype = ctypes.c_size_t
+    lib.plbm_elem_bytes.argtypes = [P]
+    lib.plbm_elem_bytes.restype = ctypes.c_size_t
+    lib.plbm_init.argtypes = [P, vp, vp, vp, vp, vp, vp]
+    lib.plbm_step.argtypes = [P, vp, vp, ctypes.c_int, D, vp]
+    lib.plbm_moments.argtypes = [P, vp, vp, vp, vp, vp, D, vp]
+    lib.plbm_dev_scales.argtypes = [P, vp, vp, vp, vp, vp]
+    lib.plbm_strerror.argtypes = [ctypes.c_int]
+    lib.plbm_strerror.restype = ctypes.c_char_p
+    lib.plbm_last_hip_error.argtypes = []
+    lib.plbm_last_hip_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+#: every symbol declared in include/plbm.h
+EXPORTED = ("plbm_coeffs", "plbm_desc_default", "plbm_buffer_elems",
+            "plbm_elem_bytes", "plbm_init", "plbm_step", "plbm_moments",
+            "plbm_dev_scales", "plbm_strerror", "plbm_last_hip_error")
+
+
+def strerror(status):
+    return lib.plbm_strerror(int(status)).decode()
+
+
+def check(status, what):
+    if status != PLBM_OK:
+        raise PlbmError(status, what)
+
+
+def coeffs(v):
+    """plbm_coeffs: c[i][j] for the velocity list v (host, FP64)."""
+    q = len(v)
+    va = (ctypes.c_double * max(q, 1))(*[float(x) for x in v])
+    ca = (ctypes.c_double * max(q * q, 1))()
+    check(lib.plbm_coeffs(q, va, ca), "plbm_coeffs")
+    return [[ca[i * q + j] for j in range(q)] for i in range(q)]
+
+
+def desc_default(dim, nx, ny, omega, storage):
+    d = PlbmDesc()
+    check(lib.plbm_desc_default(ctypes.byref(d), dim, nx, ny, float(omega),
+                                STORAGE.get(storage, storage)), "plbm_desc_default")
+    return d
+
+
+def buffer_elems(d):
+    return int(lib.plbm_buffer_elems(ctypes.byref(d)))
+
+
+def elem_bytes(d):
+    return int(lib.plbm_elem_bytes(ctypes.byref(d)))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    return ctypes.c_void_p(stream)
+
+
+def init(d, rho, ux, uy, theta, f, stream):
+    check(lib.plbm_init(ctypes.byref(d), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta),
+                        _ptr(f), _stream(stream)), "plbm_init")
+
+
+def step(d, fa, fb, nsteps, want_sums, stream):
+    sums = (ctypes.c_double * 4)() if want_sums else None
+    check(lib.plbm_step(ctypes.byref(d), _ptr(fa), _ptr(fb), int(nsteps), sums,
+                        _stream(stream)), "plbm_step")
+    return list(sums) if want_sums else None
+
+
+def moments(d, f, rho, ux, uy, theta, want_sums, stream):
+    sums = (ctypes.c_double * 4)() if want_sums else None
+    check(lib.plbm_moments(ctypes.byref(d), _ptr(f), _ptr(rho), _ptr(ux), _ptr(uy),
+                           _ptr(theta), sums, _stream(stream)), "plbm_moments")
+    return list(sums) if want_sums else None
+
+
+def dev_scales(d, rho, ux, uy, theta, stream):
+    check(lib.plbm_dev_scales(ctypes.byref(d), _ptr(rho), _ptr(ux), _ptr(uy),
+                              _ptr(theta), _stream(stream)), "plbm_dev_scales")

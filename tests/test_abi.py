@@ -1,0 +1,111 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol,
+its host-side coefficient table agrees with the oracle, and argument
+validation rejects bad calls before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1402_5487_amd import _plbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(plbm_\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    declared = _declared()
+    assert "plbm_step" in declared and "plbm_coeffs" in declared
+    for name in declared:
+        assert hasattr(_plbm.lib, name), name
+    assert set(declared) <= set(_plbm.EXPORTED) | set(getattr(_plbm, "EXPORTED_EXTRA", ()))
+
+
+@pytest.mark.parametrize("v", [(0, 1, -1, 3, -3), (0, 1, -1, 2, -2), (0, 2, -4),
+                               (1, -1, 3, -3), (0, 1, -1, 3, -3, 5, -5), (0.0, 1.4, -1.4, 2.8, -2.8)])
+def test_coeffs_match_oracle(v):
+    got = np.array(_plbm.coeffs(v))
+    ref = oracle.lagrange_coeffs(v)
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_coeffs_errors():
+    with pytest.raises(_plbm.PlbmError) as e:
+        _plbm.coeffs((0, 1, 1))
+    assert e.value.status == _plbm.PLBM_ESINGULAR
+    with pytest.raises(_plbm.PlbmError) as e:
+        _plbm.coeffs(tuple(range(9)))
+    assert e.value.status == _plbm.PLBM_EINVAL
+    assert _plbm.lib.plbm_coeffs(5, None, None) == _plbm.PLBM_EINVAL
+    assert _plbm.lib.plbm_coeffs(0, None, None) == _plbm.PLBM_EINVAL
+
+
+def test_desc_defaults_and_sizes():
+    d = _plbm.desc_default(2, 100, 60, 1.8, "f32")
+    assert d.q1d == 5 and d.bc == _plbm.PLBM_BC_PERIODIC
+    assert list(d.v)[:5] == [0, 1, -1, 3, -3]
+    assert _plbm.buffer_elems(d) == 25 * 100 * 60
+    assert _plbm.elem_bytes(d) == 4
+    d1 = _plbm.desc_default(1, 1000, 1, 1.0, "f64")
+    assert d1.bc == _plbm.PLBM_BC_ZEROGRAD
+    assert _plbm.buffer_elems(d1) == 5 * (1000 + 6)
+    assert _plbm.elem_bytes(d1) == 8
+
+
+@pytest.mark.parametrize("dim,nx,ny,omega,storage", [
+    (3, 10, 10, 1.0, "f64"), (2, 0, 10, 1.0, "f64"), (2, 10, 10, 0.0, "f64"),
+    (2, 10, 10, 2.0, "f64"), (2, 2, 10, 1.0, "f64"), (2, 10, 10, 1.0, 7)])
+def test_desc_rejects(dim, nx, ny, omega, storage):
+    with pytest.raises(_plbm.PlbmError) as e:
+        _plbm.desc_default(dim, nx, ny, omega, storage)
+    assert e.value.status == _plbm.PLBM_EINVAL
+
+
+def test_step_validates_before_launch():
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f64")
+    buf = ctypes.c_void_p(0x1000)
+    lib = _plbm.lib
+    # aliasing buffers, null buffers, negative step count, bad omega
+    assert lib.plbm_step(ctypes.byref(d), buf, buf, 1, None, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step(ctypes.byref(d), None, buf, 1, None, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), -1, None,
+                         None) == _plbm.PLBM_EINVAL
+    d.omega = 2.5
+    assert lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                         None) == _plbm.PLBM_EINVAL
+    d.omega = 1.5
+    d.v[1] = 0.5      # off-lattice velocity cannot stream
+    assert lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                         None) == _plbm.PLBM_EINVAL
+    d.v[1] = 4.0      # beyond the three ghost/halo nodes
+    assert lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                         None) == _plbm.PLBM_EINVAL
+    d.v[1] = 1.0
+    d.q1d = 3         # valid descriptor, kernels compiled for five velocities
+    d.v[0], d.v[1], d.v[2] = 0.0, 1.0, -1.0
+    assert lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                         None) == _plbm.PLBM_EUNSUPPORTED
+
+
+def test_dev_storage_rejected_in_1d():
+    d = _plbm.desc_default(1, 100, 1, 1.0, "f64")
+    d.storage = _plbm.PLBM_F16DEV
+    assert _plbm.lib.plbm_init(ctypes.byref(d), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                               None, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                               None) == _plbm.PLBM_EUNSUPPORTED
+
+
+def test_strerror():
+    assert _plbm.strerror(0) == "ok"
+    assert "non-finite" in _plbm.strerror(_plbm.PLBM_ENONFINITE)
+    assert _plbm.strerror(-99) == "unknown status"
