@@ -18,16 +18,25 @@
  *  - Velocities are in lattice units (dx = dt = 1) and must be integers for
  *    streaming.  The 1D rule uses q1d velocities in the paper's order
  *    (v_1 = 0, v_2,3 = +-a, v_4,5 = +-b, Sec. 2.4); the 2D model is the tensor
- *    product, population k = i + q1d * j moving with (v_i, v_j).
+ *    product, population k = i + q1d * j moving with (v_i, v_j).  The device
+ *    kernels are compiled for q1d = 5 and a symmetric set (0, a, -a, b, -b)
+ *    with |a|, |b| <= 3; other sets are accepted by plbm_coeffs only and make
+ *    the device calls return PLBM_EUNSUPPORTED.
  *
- * Population layout in HBM (structure of arrays, one plane per population)
- * -------------------------------------------------------------------------
- *  - dim 2: element (k, y, x) at k * nx * ny + y * nx + x, periodic in x and y.
+ * Population layout in HBM (structure of arrays at row granularity)
+ * ----------------------------------------------------------------------
+ *  - dim 2: element (k, y, x) at (y * q + k) * nx + x with q = q1d^2: lattice
+ *    row y stores the q population rows of nx nodes one after another, so a
+ *    wave reads and writes contiguous runs of each population, and the rows
+ *    a step touches for one output row are seven contiguous blocks.  Periodic
+ *    in x and y.
  *  - dim 1: element (k, x) at k * (nx + 6) + x + 3: three ghost nodes on each
  *    side of the nx real nodes (zero-gradient ends, see plbm_step).
  *  - element type: double (PLBM_F64), float (PLBM_F32), or 16-bit deviations
  *    (PLBM_F16DEV: IEEE half, PLBM_BF16DEV: bfloat16) decoded as
  *    f_k = rho0 w_k + scale[k] * h_k with w_k = r_i(0, theta0) r_j(0, theta0).
+ *    Scales are powers of two and equal within a symmetry class (the pair of
+ *    speed magnitudes |v_i|, |v_j|); plbm_dev_scales chooses them.
  *  - A population buffer holds the POST-collision populations of the last
  *    completed step; the pre-collision state of Eq. srt at node x is obtained
  *    by pulling, f_k(x) = buffer_k(x - v_k).  plbm_init writes the buffer
@@ -175,6 +184,17 @@ int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
  */
 int plbm_dev_scales(plbm_desc *d, const double *rho, const double *ux,
                     const double *uy, const double *theta, void *stream);
+
+/*
+ * plbm_stream_copy -- measurement utility (not part of the method): copies
+ * `bytes` from src to dst, 16 bytes per thread, one pass.  It calibrates the
+ * achievable HBM bandwidth and the profiler's byte counters against a kernel
+ * whose traffic is exactly 2 * bytes.
+ *   src, dst : device pointers, 16-byte aligned, non-overlapping
+ *   bytes    : a positive multiple of 16
+ * Asynchronous on `stream`.  Errors: PLBM_EINVAL, PLBM_EHIP.
+ */
+int plbm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Static description of a status code. */
 const char *plbm_strerror(int status);

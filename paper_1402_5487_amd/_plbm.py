@@ -82,6 +82,7 @@ def _load():
     lib.plbm_dev_scales.argtypes = [P, vp, vp, vp, vp, vp]
     lib.plbm_strerror.argtypes = [ctypes.c_int]
     lib.plbm_strerror.restype = ctypes.c_char_p
+    lib.plbm_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     lib.plbm_last_hip_error.argtypes = []
     lib.plbm_last_hip_error.restype = ctypes.c_char_p
     return lib
@@ -92,7 +93,8 @@ lib = _load()
 #: every symbol declared in include/plbm.h
 EXPORTED = ("plbm_coeffs", "plbm_desc_default", "plbm_buffer_elems",
             "plbm_elem_bytes", "plbm_init", "plbm_step", "plbm_moments",
-            "plbm_dev_scales", "plbm_strerror", "plbm_last_hip_error")
+            "plbm_dev_scales", "plbm_strerror", "plbm_last_hip_error",
+            "plbm_stream_copy")
 
 
 def strerror(status):
@@ -158,3 +160,9 @@ def moments(d, f, rho, ux, uy, theta, want_sums, stream):
 def dev_scales(d, rho, ux, uy, theta, stream):
     check(lib.plbm_dev_scales(ctypes.byref(d), _ptr(rho), _ptr(ux), _ptr(uy),
                               _ptr(theta), _stream(stream)), "plbm_dev_scales")
+
+
+def stream_copy(src, dst, nbytes, stream):
+    """plbm_stream_copy: the HBM calibration copy."""
+    check(lib.plbm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)),
+          "plbm_stream_copy")

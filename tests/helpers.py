@@ -22,8 +22,8 @@ def decode(buf, lat):
     base = np.array([d.rho0 * w[k % 5] * w[k // 5] for k in range(25)],
                     dtype=np.float32).astype(np.float64)
     scale = np.array([d.scale[k] for k in range(25)], dtype=np.float64)
-    g = h.float().double().numpy().reshape(25, -1)
-    return (base[:, None] + scale[:, None] * g).ravel()
+    g = h.float().double().numpy().reshape(lat.ny, 25, lat.nx)
+    return (base[None, :, None] + scale[None, :, None] * g).ravel()
 
 
 def pulled_state(buf, lat):
@@ -31,7 +31,8 @@ def pulled_state(buf, lat):
     arrays ((25, ny, nx) or (5, nx))."""
     a = decode(buf, lat)
     if lat.dim == 2:
-        a = a.reshape(25, lat.ny, lat.nx)
+        # device layout: (y * 25 + k) * nx + x
+        a = a.reshape(lat.ny, 25, lat.nx).transpose(1, 0, 2)
         out = np.empty_like(a)
         for k in range(25):
             out[k] = np.roll(a[k], (V5[k // 5], V5[k % 5]), axis=(0, 1))

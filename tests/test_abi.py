@@ -97,6 +97,33 @@ def test_step_validates_before_launch():
                          None) == _plbm.PLBM_EUNSUPPORTED
 
 
+def test_asymmetric_set_unsupported_on_device():
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f64")
+    # (0, 1, -1, 2, -3): valid table, but not the symmetric structure the
+    # kernels are compiled for
+    v = (0.0, 1.0, -1.0, 2.0, -3.0)
+    c = _plbm.coeffs(v)
+    for i in range(5):
+        d.v[i] = v[i]
+        for j in range(5):
+            d.c[i * 5 + j] = c[i][j]
+    buf = ctypes.c_void_p(0x1000)
+    assert _plbm.lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                               None) == _plbm.PLBM_EUNSUPPORTED
+
+
+def test_dev_scales_must_be_powers_of_two_per_class():
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f16dev")
+    buf = ctypes.c_void_p(0x1000)
+    d.scale[0] = 0.3     # not a power of two
+    assert _plbm.lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                               None) == _plbm.PLBM_EINVAL
+    d.scale[0] = 1.0
+    d.scale[1] = 0.5     # k = 1 and k = 2 share a class (|v_x| = 1, v_y = 0)
+    assert _plbm.lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
+                               None) == _plbm.PLBM_EINVAL
+
+
 def test_dev_storage_rejected_in_1d():
     d = _plbm.desc_default(1, 100, 1, 1.0, "f64")
     d.storage = _plbm.PLBM_F16DEV

@@ -231,8 +231,9 @@ def test_full_size_sampled_nodes(storage):
     ys = np.concatenate([rng.integers(0, n, 40), [0, 1, 2, n - 1, n - 3]])
     xs = np.concatenate([rng.integers(0, n, 40), [n - 1, 0, 255, 256, 3]])
     plane = n * n
-    src = before.view(25, n, n)
-    dst = after.view(25, n, n)
+    # device layout: (y * 25 + k) * n + x
+    src = before.view(n, 25, n).transpose(0, 1)
+    dst = after.view(n, 25, n).transpose(0, 1)
     one = oracle.Lattice(2, 1, 1, omega=1.8)
     tol = 1e-14 if storage == "f64" else 64 * EPS32
     for y, x in zip(ys, xs):
