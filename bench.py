@@ -55,6 +55,10 @@ def parse():
                     help="time one form and print its line only (for profilers)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only the 2 GiB calibration copy (for profilers)")
+    ap.add_argument("--batch-steps", type=int, default=2000,
+                    help="steps of the batching form (0 skips it)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batching form (for profilers)")
     return ap.parse_args()
 
 
@@ -141,6 +145,46 @@ def copy_bandwidth(reps=20):
     return 2 * nbytes / s / 1e9, ok
 
 
+def batch_form(steps, seed=0):
+    """256 independent KH lattices, sides drawn from {64, 96, ..., 512},
+    U0 ~ U[0.02, 0.12], theta ~ U[0.345, 0.355] (stable variant of
+    U[0.2, 0.4]), omega ~ U[1.5, 1.9]; autotuned tiles, one launch per step
+    replayed from a captured graph."""
+    import tempfile
+
+    import torch
+    from paper_1402_5487_amd import inputs
+    from paper_1402_5487_amd.batch import Batch
+    members = inputs.batch_members(256, seed=seed, theta_range=(0.345, 0.355))
+    b = Batch([(m.side, m.side, m.omega) for m in members])
+    t0 = time.perf_counter()
+    with tempfile.TemporaryDirectory() as td:
+        b.autotune(os.path.join(td, "tune.json"))
+    tune_s = time.perf_counter() - t0
+    for i, m in enumerate(members):
+        b.init(i, *inputs.kelvin_helmholtz(m.side, m.side, u0=m.u0, theta=m.theta))
+    b.step(16)                                     # warm-up, records the graph
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    b.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = b.info()
+    finite = all(bool(torch.isfinite(b.moments(i)[0]).all()) for i in range(0, 256, 17))
+    b.close()
+    nodes = info["nodes"]
+    gbs = nodes * 200 / (ms * 1e-3) / 1e9
+    return {"lattices": 256, "nodes": nodes, "steps": steps, "ms_per_step": ms,
+            "mlups": nodes / (ms * 1e-3) / 1e6, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "tiles": info["tiles"], "grid_mode": info["grid_mode"],
+            "lds_bytes": info["lds_bytes"], "graph_steps": info["graph_steps"],
+            "tile_shapes": {str(k): list(v) for k, v in sorted(info["classes"].items())},
+            "autotune_s": tune_s, "finite_sampled": finite}
+
+
 def cpu_baseline(n, fields, steps):
     import oracle
     lat = oracle.Lattice(2, n, n, omega=1.8)
@@ -169,6 +213,10 @@ def main():
         print(json.dumps({"copy_gbs": round(gbs, 1), "ok": ok}), flush=True)
         return
 
+    if args.batch_only:
+        print(json.dumps(batch_form(args.batch_steps)), flush=True)
+        return
+
     n = args.size
     fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80.0, theta=args.theta)
     forms = args.forms.split(",") if args.only is None else [args.only]
@@ -185,6 +233,10 @@ def main():
     for k, v in acc.items():
         results[k]["max_abs_err_vs_f64"] = v
     copy_gbs, copy_ok = copy_bandwidth()
+    batch = None
+    if args.batch_steps > 0:
+        log(f"batching form, {args.batch_steps} steps")
+        batch = batch_form(args.batch_steps)
 
     head = "f16dev" if "f16dev" in results else forms[0]
     h = results[head]
@@ -227,6 +279,7 @@ def main():
         "forms": rnd(results),
         "vs_fp64_speedup": round(h["mlups"] / results["f64"]["mlups"], 3)
         if "f64" in results else None,
+        "batch": rnd(batch) if batch else None,
         "copy_gbs": round(copy_gbs, 1),
         "copy_ok": copy_ok,
         "kernel_sha256_16": kernel_hash(),

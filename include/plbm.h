@@ -185,6 +185,88 @@ int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
 int plbm_dev_scales(plbm_desc *d, const double *rho, const double *ux,
                     const double *uy, const double *theta, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batching form: many independent D2Q25 lattices advanced together.
+ * Each lattice is the model of plbm_step (same velocity set and table) with
+ * its own size and relaxation constant, FP32 storage, periodic boundaries.
+ * One kernel launch per step walks a work list of tiles of every lattice;
+ * plbm_batch_step replays a captured hipGraph of several such launches.
+ * ------------------------------------------------------------------------ */
+typedef struct plbm_batch plbm_batch;          /* opaque, owned by the library */
+
+typedef struct plbm_lattice_spec {
+    int32_t nx, ny;
+    double omega;
+} plbm_lattice_spec;
+
+#define PLBM_BATCH_MAX_CLASSES 32
+
+typedef struct plbm_batch_info {
+    int32_t count;              /* lattices */
+    int32_t tiles;              /* work-list entries */
+    int32_t grid_mode;          /* 0: one workgroup per tile; k: k per CU */
+    int32_t lds_bytes;          /* LDS reserved per workgroup (occupancy cap) */
+    int32_t graph_steps;        /* launches per captured graph (0: no graph) */
+    int32_t parity;             /* which of the two buffers holds the state */
+    int64_t nodes;              /* total lattice nodes */
+    int64_t pool_bytes;         /* device memory of all population buffers */
+    int32_t classes;            /* size classes with a chosen tile shape */
+    int32_t class_size[PLBM_BATCH_MAX_CLASSES];
+    int32_t class_w[PLBM_BATCH_MAX_CLASSES];   /* tile width in nodes */
+    int32_t class_r[PLBM_BATCH_MAX_CLASSES];   /* passes of 256/w rows */
+} plbm_batch_info;
+
+/*
+ * plbm_batch_create -- allocate `count` lattices (two FP32 buffers each, one
+ * device pool owned by the batch) described by specs[i] (host array) with
+ * the velocity set and table of *proto (proto->storage must be PLBM_F32,
+ * dim 2; its nx, ny, omega are ignored).  Tiles start at 256 x 1 until
+ * plbm_batch_autotune chooses shapes.  Synchronous.  *out receives the handle.
+ * Errors: PLBM_EINVAL (bad spec), PLBM_EUNSUPPORTED, PLBM_EHIP.
+ */
+int plbm_batch_create(const plbm_desc *proto, const plbm_lattice_spec *specs, int count,
+                      plbm_batch **out);
+
+/* Free the batch and its device memory (synchronises the device). */
+int plbm_batch_destroy(plbm_batch *b);
+
+/* Initialise lattice i to the equilibrium of its fields, as plbm_init
+ * (rho, ux, uy, theta: device pointers to nx*ny doubles). Asynchronous. */
+int plbm_batch_init(plbm_batch *b, int i, const double *rho, const double *ux,
+                    const double *uy, const double *theta, void *stream);
+
+/*
+ * plbm_batch_autotune -- choose, per size class (max(nx, ny)), the tile
+ * shape (width 64/128/256 nodes, 1/2/4 passes) and then the grid mode and
+ * LDS occupancy cap, by timing launches on this batch.  cache_path (nullable)
+ * names a JSON file read first (entries for this architecture are reused
+ * without timing) and rewritten with the choices.  Overwrites every
+ * population buffer (call before plbm_batch_init).  Synchronises `stream`.
+ */
+int plbm_batch_autotune(plbm_batch *b, const char *cache_path, void *stream);
+
+/* Launches recorded per graph (even, 0..64; 0 disables graphs; default 8). */
+int plbm_batch_set_graph_steps(plbm_batch *b, int steps);
+
+/*
+ * plbm_batch_step -- advance every lattice by nsteps applications of
+ * Eq. srt (as plbm_step).  Whole groups of graph_steps steps replay the
+ * captured graph (recorded on first use); the rest are direct launches.
+ * Asynchronous on `stream`.
+ */
+int plbm_batch_step(plbm_batch *b, int nsteps, void *stream);
+
+/* Moments (and optional host sums) of lattice i, as plbm_moments. */
+int plbm_batch_moments(const plbm_batch *b, int i, double *rho, double *ux, double *uy,
+                       double *theta, double *sums, void *stream);
+
+/* Descriptor of lattice i (may be NULL) and its current population buffer
+ * (device pointer, valid until the next step; may be NULL). */
+int plbm_batch_lattice(const plbm_batch *b, int i, plbm_desc *desc, void **f);
+
+/* Sizes, tiles and the tuned configuration. */
+int plbm_batch_query(const plbm_batch *b, plbm_batch_info *info);
+
 /*
  * plbm_stream_copy -- measurement utility (not part of the method): copies
  * `bytes` from src to dst, 16 bytes per thread, one pass.  It calibrates the

@@ -166,3 +166,46 @@ def stream_copy(src, dst, nbytes, stream):
     """plbm_stream_copy: the HBM calibration copy."""
     check(lib.plbm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)),
           "plbm_stream_copy")
+
+
+# ---------------------------------------------------------------------------
+# batching form
+# ---------------------------------------------------------------------------
+class LatticeSpec(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("omega", ctypes.c_double)]
+
+
+BATCH_MAX_CLASSES = 32
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("grid_mode", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32), ("parity", ctypes.c_int32),
+                ("nodes", ctypes.c_int64), ("pool_bytes", ctypes.c_int64),
+                ("classes", ctypes.c_int32),
+                ("class_size", ctypes.c_int32 * BATCH_MAX_CLASSES),
+                ("class_w", ctypes.c_int32 * BATCH_MAX_CLASSES),
+                ("class_r", ctypes.c_int32 * BATCH_MAX_CLASSES)]
+
+
+def _setup_batch(lib):
+    vp, P = ctypes.c_void_p, ctypes.POINTER(PlbmDesc)
+    lib.plbm_batch_create.argtypes = [P, ctypes.POINTER(LatticeSpec), ctypes.c_int,
+                                      ctypes.POINTER(vp)]
+    lib.plbm_batch_destroy.argtypes = [vp]
+    lib.plbm_batch_init.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.plbm_batch_autotune.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.plbm_batch_set_graph_steps.argtypes = [vp, ctypes.c_int]
+    lib.plbm_batch_step.argtypes = [vp, ctypes.c_int, vp]
+    lib.plbm_batch_moments.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp,
+                                       ctypes.POINTER(ctypes.c_double), vp]
+    lib.plbm_batch_lattice.argtypes = [vp, ctypes.c_int, P, ctypes.POINTER(vp)]
+    lib.plbm_batch_query.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+
+
+_setup_batch(lib)
+EXPORTED = EXPORTED + ("plbm_batch_create", "plbm_batch_destroy", "plbm_batch_init",
+                       "plbm_batch_autotune", "plbm_batch_set_graph_steps",
+                       "plbm_batch_step", "plbm_batch_moments", "plbm_batch_lattice",
+                       "plbm_batch_query")
