@@ -237,7 +237,7 @@ int plbm_batch_init(plbm_batch *b, int i, const double *rho, const double *ux,
 
 /*
  * plbm_batch_autotune -- choose, per size class (max(nx, ny)), the tile
- * shape (width 64/128/256 nodes, 1/2/4 passes) and then the grid mode and
+ * shape (width 64/128/256 nodes, 1/2/4/8 passes) and then the grid mode and
  * LDS occupancy cap, by timing launches on this batch.  cache_path (nullable)
  * names a JSON file read first (entries for this architecture are reused
  * without timing) and rewritten with the choices.  Overwrites every
@@ -266,6 +266,86 @@ int plbm_batch_lattice(const plbm_batch *b, int i, plbm_desc *desc, void **f);
 
 /* Sizes, tiles and the tuned configuration. */
 int plbm_batch_query(const plbm_batch *b, plbm_batch_info *info);
+
+/* ------------------------------------------------------------------------
+ * Learned closure: a 3-layer 3x3 convolutional network (25 -> 32 -> 32 -> 25
+ * channels, ReLU, periodic padding; BF16 MFMA with FP32 accumulation) that
+ * corrects a coarse FP32 D2Q25 lattice's post-collision populations P:
+ *   P <- P + Pi(s * CNN((P - mean) / scale))
+ * where Pi removes, node by node, the correction's mass, momentum and energy
+ * (the collision invariants), so a corrected step still conserves them.
+ * Training targets come from restricted fine-lattice runs (plbm_restrict).
+ * ------------------------------------------------------------------------ */
+typedef struct plbm_closure plbm_closure;      /* opaque, owns workspaces */
+
+/* Flat FP32 parameter vector: for layer l = 0, 1, 2 at offset l * 9248,
+ * weights W[tap][out][in] (9 x 32 x 32, tap = 3 * (dy + 1) + (dx + 1), the
+ * input node is (y + dy, x + dx)) then the bias[32].  Channels are padded to
+ * 32; the padded inputs of layer 0 and outputs of layer 2 must hold zeros. */
+#define PLBM_CNN_LAYER_PARAMS 9248
+#define PLBM_CNN_PARAMS (3 * PLBM_CNN_LAYER_PARAMS)
+
+/*
+ * plbm_closure_create -- workspaces for up to `frames` coarse lattices of
+ * the shape of *coarse (dim 2, FP32 storage, nx a multiple of 64) processed
+ * together.  Synchronous.  Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_EHIP.
+ */
+int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_closure **out);
+int plbm_closure_destroy(plbm_closure *c);
+
+/* Normalisation (host arrays of 25): network input (P_k - in_mean[k]) /
+ * in_scale[k]; correction s_k * y_k with s_k = out_scale[k]. */
+int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, const float *in_scale,
+                          const float *out_scale);
+
+/*
+ * plbm_closure_forward -- run the network on `frames` post-collision buffers
+ * (post: host array of device pointers, each a population buffer of the
+ * coarse lattice) with parameters `params` (device, PLBM_CNN_PARAMS floats).
+ * Keeps the activations for plbm_closure_backward / plbm_closure_apply.
+ */
+int plbm_closure_forward(plbm_closure *c, const float *params, const float *const *post,
+                         int frames, void *stream);
+
+/*
+ * plbm_closure_backward -- loss L = mean over nodes of
+ * sum_k ((Pi(s y) - Pi(target - post))_k / s_k)^2 for the last forward pass
+ * and its gradient with respect to `params`, written to `grads` (device,
+ * PLBM_CNN_PARAMS floats).  target: host array of device pointers to the
+ * desired post-collision buffers.  loss: NULL, or a host double receiving L
+ * (synchronises `stream`; PLBM_ENONFINITE if not finite).
+ */
+int plbm_closure_backward(plbm_closure *c, const float *params, const float *const *post,
+                          const float *const *target, float *grads, double *loss, void *stream);
+
+/* One Adam step (step count t >= 1) on device arrays of PLBM_CNN_PARAMS. */
+int plbm_closure_adam(plbm_closure *c, float *params, const float *grads, float *m, float *v,
+                      int t, float lr, float b1, float b2, float eps, void *stream);
+
+/*
+ * plbm_closure_apply -- add the projected correction of the last forward pass
+ * to the same post buffers, in place.  Fallback: a node whose correction is
+ * not finite or exceeds bound * s_k in any component keeps its plain
+ * post-collision populations, and *skipped (device counter, nullable) is
+ * incremented.
+ */
+int plbm_closure_apply(plbm_closure *c, float *const *post, int frames, float bound,
+                       unsigned *skipped, void *stream);
+
+/* Device pointer and size of an internal activation (for tests):
+ * 0 input, 1 layer-1 output, 2 layer-2 output (bf16 NHWC x 32), 3 network
+ * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs. */
+int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes);
+
+/*
+ * plbm_restrict -- block means over factor x factor fine nodes of rho,
+ * rho u and rho (2 theta + |u|^2), returned as coarse (rho, u, theta).
+ * All pointers are device FP64 arrays; fine fields fnx x fny (multiples of
+ * factor).  Asynchronous.
+ */
+int plbm_restrict(const double *rho, const double *ux, const double *uy, const double *theta,
+                  int fnx, int fny, int factor, double *crho, double *cux, double *cuy,
+                  double *ctheta, void *stream);
 
 /*
  * plbm_stream_copy -- measurement utility (not part of the method): copies

@@ -1,0 +1,115 @@
+"""FP64 reference of the learned closure (TEST INFRASTRUCTURE ONLY).
+
+The closure is the learned form of the build: a 3-layer 3x3 convolutional
+network that maps a coarse lattice's normalised post-collision populations to
+a correction of them.  The paper has no such network; this module is the
+plain, slow definition the GPU kernels are checked against:
+
+  conv3x3 with periodic padding:
+      out[y, x, o] = b[o] + sum_{dy, dx in {-1, 0, 1}} sum_i
+                     in[(y + dy) mod H, (x + dx) mod W, i] * w[dy + 1, dx + 1, i, o]
+  network: conv(25 -> 32), ReLU, conv(32 -> 32), ReLU, conv(32 -> 25)
+  projection: per node, remove from a 25-vector its components along the
+      conserved moments phi = (1, v_x, v_y, |v|^2) of the D2Q25 velocities,
+      Pi = I - Phi (Phi^T Phi)^-1 Phi^T (Eq. srt conserves exactly these, so a
+      projected correction leaves mass, momentum and energy unchanged)
+  loss: mean over nodes of sum_k ((Pi(s * y) - Pi(t))_k / s_k)^2
+  Adam (Kingma & Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+      p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+  restriction: 4 x 4 block means of rho, rho u and sum f |v|^2.
+
+Arrays are float64 numpy, images (H, W, C).
+"""
+import numpy as np
+
+V5 = np.array([0.0, 1.0, -1.0, 3.0, -3.0])
+
+
+def velocities_2d():
+    """(25, 2) velocities of population k = i + 5 j."""
+    return np.array([[V5[k % 5], V5[k // 5]] for k in range(25)])
+
+
+def projection():
+    """Pi (25 x 25) onto the complement of span{1, v_x, v_y, |v|^2}."""
+    v = velocities_2d()
+    phi = np.stack([np.ones(25), v[:, 0], v[:, 1], (v ** 2).sum(1)], axis=1)
+    return np.eye(25) - phi @ np.linalg.solve(phi.T @ phi, phi.T)
+
+
+def conv3x3(x, w, b):
+    """Periodic 3x3 convolution (cross-correlation), written out."""
+    H, W, _ = x.shape
+    out = np.broadcast_to(b, (H, W, w.shape[3])).astype(np.float64).copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            shifted = np.roll(x, shift=(-dy, -dx), axis=(0, 1))   # shifted[y,x] = x[y+dy, x+dx]
+            out += shifted @ w[dy + 1, dx + 1]
+    return out
+
+
+def conv3x3_backward(x, w, dout):
+    """Gradients of conv3x3 w.r.t. its input, weights and bias."""
+    dx = np.zeros_like(x)
+    dw = np.zeros_like(w)
+    for dy in (-1, 0, 1):
+        for ddx in (-1, 0, 1):
+            shifted = np.roll(x, shift=(-dy, -ddx), axis=(0, 1))
+            dw[dy + 1, ddx + 1] = np.einsum("yxi,yxo->io", shifted, dout)
+            # out[y,x] gets x[y+dy, x+dx] w  =>  dx[y', x'] += dout[y'-dy, x'-dx] w^T
+            dx += np.roll(dout @ w[dy + 1, ddx + 1].T, shift=(dy, ddx), axis=(0, 1))
+    return dx, dw, dout.sum(axis=(0, 1))
+
+
+def forward(params, x):
+    """params: list of three (w, b); returns (y, cache)."""
+    (w1, b1), (w2, b2), (w3, b3) = params
+    z1 = conv3x3(x, w1, b1)
+    a1 = np.maximum(z1, 0.0)
+    z2 = conv3x3(a1, w2, b2)
+    a2 = np.maximum(z2, 0.0)
+    y = conv3x3(a2, w3, b3)
+    return y, (x, z1, a1, z2, a2)
+
+
+def backward(params, cache, dy):
+    (w1, _), (w2, _), (w3, _) = params
+    x, z1, a1, z2, a2 = cache
+    da2, dw3, db3 = conv3x3_backward(a2, w3, dy)
+    dz2 = da2 * (z2 > 0)
+    da1, dw2, db2 = conv3x3_backward(a1, w2, dz2)
+    dz1 = da1 * (z1 > 0)
+    _, dw1, db1 = conv3x3_backward(x, w1, dz1)
+    return [(dw1, db1), (dw2, db2), (dw3, db3)]
+
+
+def loss_and_grad(y, target, scale):
+    """Projected, scale-weighted squared error and its gradient w.r.t. y.
+    y: (H, W, 25) network output (normalised units); target: (H, W, 25)
+    correction in physical units; scale: (25,) s_k."""
+    P = projection()
+    s = np.asarray(scale, dtype=np.float64)
+    r = (y * s) @ P.T - target @ P.T                  # Pi(s y) - Pi(t)
+    n = y.shape[0] * y.shape[1]
+    loss = ((r / s) ** 2).sum() / n
+    dy = ((r / s ** 2) @ P) * s * 2.0 / n             # Pi symmetric
+    return loss, dy
+
+
+def adam(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def restrict(rho, jx, jy, e, factor=4):
+    """Block means of the conserved fields; returns coarse (rho, ux, uy,
+    theta) with 2 rho theta = E - rho |u|^2 (two dimensions)."""
+    def bm(a):
+        H, W = a.shape
+        return a.reshape(H // factor, factor, W // factor, factor).mean(axis=(1, 3))
+    r, X, Y, E = bm(rho), bm(jx), bm(jy), bm(e)
+    ux, uy = X / r, Y / r
+    return r, ux, uy, (E / r - ux * ux - uy * uy) / 2.0

@@ -209,3 +209,34 @@ EXPORTED = EXPORTED + ("plbm_batch_create", "plbm_batch_destroy", "plbm_batch_in
                        "plbm_batch_autotune", "plbm_batch_set_graph_steps",
                        "plbm_batch_step", "plbm_batch_moments", "plbm_batch_lattice",
                        "plbm_batch_query")
+
+
+# ---------------------------------------------------------------------------
+# learned closure
+# ---------------------------------------------------------------------------
+CNN_LAYER_PARAMS = 9248
+CNN_PARAMS = 3 * CNN_LAYER_PARAMS
+
+
+def _setup_closure(lib):
+    vp, P = ctypes.c_void_p, ctypes.POINTER(PlbmDesc)
+    F = ctypes.POINTER(ctypes.c_float)
+    lib.plbm_closure_create.argtypes = [P, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.plbm_closure_destroy.argtypes = [vp]
+    lib.plbm_closure_set_norm.argtypes = [vp, F, F, F]
+    lib.plbm_closure_forward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.plbm_closure_backward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                          ctypes.POINTER(ctypes.c_double), vp]
+    lib.plbm_closure_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+    lib.plbm_closure_apply.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_float, vp, vp]
+    lib.plbm_closure_activation.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp),
+                                            ctypes.POINTER(ctypes.c_size_t)]
+    lib.plbm_restrict.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  vp, vp, vp, vp, vp]
+
+
+_setup_closure(lib)
+EXPORTED = EXPORTED + ("plbm_closure_create", "plbm_closure_destroy", "plbm_closure_set_norm",
+                       "plbm_closure_forward", "plbm_closure_backward", "plbm_closure_adam",
+                       "plbm_closure_apply", "plbm_closure_activation", "plbm_restrict")

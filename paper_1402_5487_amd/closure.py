@@ -1,0 +1,125 @@
+"""Learned closure over libplbm: argument marshalling for plbm_closure_* and
+plbm_restrict.  Parameters, gradients and Adam moments are torch float32
+device tensors of PLBM_CNN_PARAMS entries (layout in include/plbm.h)."""
+import ctypes
+
+import torch
+
+from . import _plbm
+
+CNN_PARAMS = _plbm.CNN_PARAMS
+LAYER = _plbm.CNN_LAYER_PARAMS
+CH = 32
+
+
+def _ptrs(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def init_params(seed=0, device="cuda:0", out_gain=0.1):
+    """He-uniform weights on the real channels (25 inputs of layer 1, 25
+    outputs of layer 3), zero in the padding and in the biases."""
+    g = torch.Generator().manual_seed(seed)
+    p = torch.zeros(CNN_PARAMS, dtype=torch.float32)
+    for layer, (cin, cout) in enumerate(((25, 32), (32, 32), (32, 25))):
+        w = torch.zeros(9, CH, CH)
+        bound = (6.0 / (9 * cin)) ** 0.5 * (out_gain if layer == 2 else 1.0)
+        w[:, :cout, :cin] = (torch.rand(9, cout, cin, generator=g) * 2 - 1) * bound
+        p[layer * LAYER:layer * LAYER + 9 * CH * CH] = w.reshape(-1)
+    return p.to(device)
+
+
+def split_params(p):
+    """Flat vector -> [(w[3,3,in,out], b[out]) x 3] float64 numpy (oracle form)."""
+    import numpy as np
+    q = p.detach().double().cpu().numpy()
+    out = []
+    for layer, (cin, cout) in enumerate(((25, 32), (32, 32), (32, 25))):
+        w = q[layer * LAYER:layer * LAYER + 9 * CH * CH].reshape(9, CH, CH)   # [t][o][i]
+        b = q[layer * LAYER + 9 * CH * CH:(layer + 1) * LAYER]
+        wt = np.transpose(w, (0, 2, 1)).reshape(3, 3, CH, CH)                 # [dy][dx][i][o]
+        out.append((wt[:, :, :cin, :cout].copy(), b[:cout].copy()))
+    return out
+
+
+class Closure:
+    def __init__(self, nx, ny, frames, device="cuda:0"):
+        self.device = torch.device(device)
+        self.desc = _plbm.desc_default(2, nx, ny, 1.9, "f32")
+        h = ctypes.c_void_p()
+        _plbm.check(_plbm.lib.plbm_closure_create(ctypes.byref(self.desc), int(frames),
+                                                  ctypes.byref(h)), "plbm_closure_create")
+        self.handle = h
+        self.nx, self.ny, self.frames = nx, ny, frames
+        self._nf = 0
+
+    def close(self):
+        if self.handle:
+            _plbm.lib.plbm_closure_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_norm(self, in_mean, in_scale, out_scale):
+        arr = [(ctypes.c_float * 25)(*[float(v) for v in a]) for a in (in_mean, in_scale, out_scale)]
+        _plbm.check(_plbm.lib.plbm_closure_set_norm(self.handle, *arr), "plbm_closure_set_norm")
+
+    def forward(self, params, posts):
+        self._nf = len(posts)
+        _plbm.check(_plbm.lib.plbm_closure_forward(self.handle, ctypes.c_void_p(params.data_ptr()),
+                                                   _ptrs(posts), len(posts), _stream(self.device)),
+                    "plbm_closure_forward")
+
+    def backward(self, params, posts, targets, grads, want_loss=True):
+        loss = ctypes.c_double() if want_loss else None
+        _plbm.check(_plbm.lib.plbm_closure_backward(
+            self.handle, ctypes.c_void_p(params.data_ptr()), _ptrs(posts), _ptrs(targets),
+            ctypes.c_void_p(grads.data_ptr()), ctypes.byref(loss) if want_loss else None,
+            _stream(self.device)), "plbm_closure_backward")
+        return loss.value if want_loss else None
+
+    def adam(self, params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        _plbm.check(_plbm.lib.plbm_closure_adam(
+            self.handle, *[ctypes.c_void_p(a.data_ptr()) for a in (params, grads, m, v)], int(t),
+            float(lr), float(b1), float(b2), float(eps), _stream(self.device)), "plbm_closure_adam")
+
+    def apply(self, posts, bound=8.0, skipped=None):
+        _plbm.check(_plbm.lib.plbm_closure_apply(
+            self.handle, _ptrs(posts), len(posts), float(bound),
+            None if skipped is None else ctypes.c_void_p(skipped.data_ptr()),
+            _stream(self.device)), "plbm_closure_apply")
+
+    def activation(self, which):
+        """Copy of an internal activation: bf16 NHWC (which 0..2, 4..6) as
+        float32 (frames, ny, nx, 32), or the FP32 output (which 3)."""
+        ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
+        _plbm.check(_plbm.lib.plbm_closure_activation(self.handle, int(which), ctypes.byref(ptr),
+                                                      ctypes.byref(nbytes)), "activation")
+        n = self.frames * self.ny * self.nx * CH
+        if which == 3:
+            out = torch.empty(n, dtype=torch.float32, device=self.device)
+        else:
+            out = torch.empty(n, dtype=torch.bfloat16, device=self.device)
+        _plbm.check(_plbm.lib.plbm_stream_copy(ptr, ctypes.c_void_p(out.data_ptr()), nbytes.value,
+                                               _stream(self.device)), "copy")
+        return out.float().reshape(self.frames, self.ny, self.nx, CH)[:max(self._nf, 1)]
+
+
+def restrict(rho, ux, uy, theta, factor=4):
+    """Coarse (rho, u, theta) from fine FP64 device fields (plbm_restrict)."""
+    fny, fnx = rho.shape
+    out = [torch.empty((fny // factor, fnx // factor), dtype=torch.float64, device=rho.device)
+           for _ in range(4)]
+    _plbm.check(_plbm.lib.plbm_restrict(*[ctypes.c_void_p(t.data_ptr()) for t in (rho, ux, uy, theta)],
+                                        fnx, fny, factor,
+                                        *[ctypes.c_void_p(t.data_ptr()) for t in out],
+                                        _stream(rho.device)), "plbm_restrict")
+    return tuple(out)

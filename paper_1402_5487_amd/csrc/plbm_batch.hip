@@ -5,7 +5,8 @@
 //    in the row-interleaved layout of the single-lattice step.
 //  * A host-built work list holds every tile of every lattice.  A tile is W
 //    nodes wide (64, 128 or 256: one to four waves per row) and 256/W rows
-//    per pass, R passes; its shape is chosen per size class.  One kernel
+//    per pass, R passes (1, 2, 4 or 8); its shape is chosen per size class.
+//    Each entry carries its lattice's buffers and parameters.  One kernel
 //    launch walks the whole list, each block taking tile
 //    it * gridDim.x + (XCD-contiguous slot), so a grid of one block per tile
 //    and a persistent grid of a few blocks per CU are the same kernel.
@@ -42,22 +43,25 @@ struct BLat {
     int pad;
 };
 
+// A work-list entry carries its lattice's buffers and parameters, so a block
+// needs one scalar load before it starts streaming.
 struct BTile {
-    int lat;
+    float *buf[2];
+    int nx, ny;
+    float omega;
     int x0, y0;
     int shape;          // log2(W / 64) in bits 0..1, R in bits 8..15
 };
 
 constexpr int BATCH_SHAPES_W[3] = {64, 128, 256};
-constexpr int BATCH_R[3] = {1, 2, 4};
+constexpr int BATCH_R[4] = {1, 2, 4, 8};
 
-__device__ __forceinline__ void batch_tile(const BLat &L, const BTile &t, const KParams &proto,
-                                           int parity)
+__device__ __forceinline__ void batch_tile(const BTile &t, const KParams &proto, int parity)
 {
     KParams q = proto;
-    q.nx = L.nx;
-    q.ny = L.ny;
-    q.r32.omega = L.omega;
+    q.nx = t.nx;
+    q.ny = t.ny;
+    q.r32.omega = t.omega;
     const int lw = t.shape & 3, R = (t.shape >> 8) & 0xff;
     const int wpr = 1 << lw;                       // waves per row
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -65,19 +69,17 @@ __device__ __forceinline__ void batch_tile(const BLat &L, const BTile &t, const 
     const int y_first = t.y0 + (w >> lw);
     const int y_step = 4 >> lw;                    // rows per pass
     double acc[4];
-    step_rows<StF32, 1, false>(L.buf[parity], L.buf[parity ^ 1], q, xb, y_first, y_step, R, acc);
+    step_rows<StF32, 1, false>(t.buf[parity], t.buf[parity ^ 1], q, xb, y_first, y_step, R, acc);
 }
 
-__global__ __launch_bounds__(TX) void k_step_batch(const BLat *__restrict__ lats,
-                                                   const BTile *__restrict__ tiles, int ntiles,
+__global__ __launch_bounds__(TX) void k_step_batch(const BTile *__restrict__ tiles, int ntiles,
                                                    KParams proto, int parity)
 {
     const int slot = xcd_tile(blockIdx.x, gridDim.x);
 #pragma unroll 1
     for (int i = slot; i < ntiles; i += gridDim.x) {
         const BTile t = tiles[i];
-        const BLat L = lats[t.lat];
-        batch_tile(L, t, proto, parity);
+        batch_tile(t, proto, parity);
     }
 }
 
@@ -111,7 +113,6 @@ struct plbm_batch {
     KParams kp;                      // kernel parameters shared by all lattices
     std::vector<plbm_lattice_spec> specs;
     std::vector<BLat> lats;          // host copy of the lattice table
-    BLat *d_lats = nullptr;
     BTile *d_tiles = nullptr;
     int ntiles = 0;
     float *pool = nullptr;
@@ -138,6 +139,20 @@ size_t padded_elems(const plbm_lattice_spec &s)
     return (n + 63) / 64 * 64;
 }
 
+BTile make_tile(const BLat &L, int x0, int y0, int shape)
+{
+    BTile t;
+    t.buf[0] = L.buf[0];
+    t.buf[1] = L.buf[1];
+    t.nx = L.nx;
+    t.ny = L.ny;
+    t.omega = L.omega;
+    t.x0 = x0;
+    t.y0 = y0;
+    t.shape = shape;
+    return t;
+}
+
 int build_tiles(plbm_batch *b)
 {
     std::vector<BTile> tiles;
@@ -149,7 +164,7 @@ int build_tiles(plbm_batch *b)
         const int h = (256 / sc.w) * sc.r;
         for (int y0 = 0; y0 < b->specs[i].ny; y0 += h)
             for (int x0 = 0; x0 < b->specs[i].nx; x0 += sc.w)
-                tiles.push_back(BTile{(int)i, x0, y0, lw | (sc.r << 8)});
+                tiles.push_back(make_tile(b->lats[i], x0, y0, lw | (sc.r << 8)));
     }
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     b->d_tiles = nullptr;
@@ -174,8 +189,8 @@ int grid_of(const plbm_batch *b, int ntiles)
 int launch_batch(plbm_batch *b, const BTile *tiles, int ntiles, int parity, hipStream_t st)
 {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_step_batch, dim3(grid_of(b, ntiles)), dim3(TX), b->lds, st, b->d_lats, tiles,
-                       ntiles, b->kp, parity);
+    hipLaunchKernelGGL(k_step_batch, dim3(grid_of(b, ntiles)), dim3(TX), b->lds, st, tiles, ntiles,
+                       b->kp, parity);
     return hipck(hipGetLastError());
 }
 
@@ -209,7 +224,8 @@ bool read_cache(const char *path, const std::string &arch, std::map<std::string,
         int cls = 0, w = 0, r = 0, m = 0, l = 0;
         if (std::sscanf(obj.c_str(), "{\"arch\": \"%63[^\"]\", \"storage\": \"%15[^\"]\", \"class\": %d, "
                                      "\"w\": %d, \"r\": %d}", a, stor, &cls, &w, &r) == 5) {
-            if (std::string(stor) == "f32" && (w == 64 || w == 128 || w == 256) && r >= 1 && r <= 8)
+            if (std::string(stor) == "f32" && (w == 64 || w == 128 || w == 256) && r >= 1 && r <= 8 &&
+                (r & (r - 1)) == 0)
                 out[std::string(a) + "/f32/" + std::to_string(cls)] = ShapeChoice{w, r};
         } else if (std::sscanf(obj.c_str(), "{\"arch\": \"%63[^\"]\", \"mode\": %d, \"lds\": %d}", a, &m,
                                &l) == 3) {
@@ -323,9 +339,6 @@ extern "C" int plbm_batch_create(const plbm_desc *proto, const plbm_lattice_spec
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipMalloc((void **)&b->d_lats, b->lats.size() * sizeof(BLat)) != hipSuccess ||
-        hipMemcpy(b->d_lats, b->lats.data(), b->lats.size() * sizeof(BLat), hipMemcpyHostToDevice) !=
-            hipSuccess ||
         hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
         plbm_batch_destroy(b);
         return PLBM_EHIP;
@@ -346,7 +359,6 @@ extern "C" int plbm_batch_destroy(plbm_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
-    if (b->d_lats) (void)hipFree(b->d_lats);
     if (b->pool) (void)hipFree(b->pool);
     delete b;
     return PLBM_OK;
@@ -470,7 +482,7 @@ extern "C" int plbm_batch_autotune(plbm_batch *b, const char *cache_path, void *
         float best = 1e30f;
         ShapeChoice choice;
         for (int wi = 0; wi < 3; ++wi)
-            for (int ri = 0; ri < 3; ++ri) {
+            for (int ri = 0; ri < 4; ++ri) {
                 const int w = BATCH_SHAPES_W[wi], r = BATCH_R[ri];
                 if (w > 2 * kv.first && w != 64) continue;
                 std::vector<BTile> tl;
@@ -478,7 +490,7 @@ extern "C" int plbm_batch_autotune(plbm_batch *b, const char *cache_path, void *
                 for (int li : kv.second)
                     for (int y0 = 0; y0 < b->specs[li].ny; y0 += h)
                         for (int x0 = 0; x0 < b->specs[li].nx; x0 += w)
-                            tl.push_back(BTile{li, x0, y0, lw | (r << 8)});
+                            tl.push_back(make_tile(b->lats[li], x0, y0, lw | (r << 8)));
                 BTile *dt = nullptr;
                 rc = hipck(hipMalloc((void **)&dt, tl.size() * sizeof(BTile)));
                 if (rc != PLBM_OK) return rc;

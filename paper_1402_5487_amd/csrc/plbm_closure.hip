@@ -1,0 +1,686 @@
+// libplbm learned closure: a 3-layer 3x3 convolutional network (25 -> 32 ->
+// 32 -> 25 channels, ReLU between layers, periodic padding) that maps a coarse
+// lattice's normalised post-collision populations to a correction of them,
+// with hand-written BF16 MFMA kernels for inference and training.
+//
+//  * Activations are NHWC bf16 with the channel count padded to 32: one node
+//    is 64 contiguous bytes.  Weights (FP32 master copy owned by the caller)
+//    are cast to two bf16 copies, [tap][out][in] for the forward pass and
+//    [tap][in][out] for the input gradient.
+//  * Convolution = implicit GEMM on v_mfma_f32_32x32x16_bf16: one wave
+//    computes 32 nodes of a row x 32 channels; K = 9 taps x 32 channels is
+//    18 MFMAs, each fed by one 16-byte load per lane of the (shifted) input
+//    node and one of the weights.  The input gradient is the same kernel with
+//    the taps mirrored and the transposed weights; the ReLU derivative is
+//    applied in its epilogue.
+//  * Weight gradient: a workgroup stages, row by row, the dZ row and the
+//    three input rows it needs in LDS channel-major (transposed), and each
+//    wave accumulates 32 x 32 x (64 nodes) MFMA products for its taps; block
+//    partials are summed in a fixed order (deterministic).
+//  * Loss, projection and apply are per-node kernels: the projection removes
+//    the correction's mass, momentum and energy (the invariants of the
+//    collision), so an applied correction conserves them exactly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "plbm_device.h"
+#include "plbm_internal.h"
+
+struct plbm_closure;
+
+namespace {
+
+constexpr int CH = 32;          // padded channels
+constexpr int CREAL = 25;       // populations
+constexpr int TAPS = 9;
+constexpr int LAYER_W = TAPS * CH * CH;
+constexpr int LAYER_P = LAYER_W + CH;          // weights + bias, per layer
+constexpr int NPARAM = 3 * LAYER_P;
+constexpr int WG_ROWS = 16;                    // rows per weight-gradient block
+constexpr int WG_SEG = 64;                     // nodes per weight-gradient row segment
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint16_t u16;
+
+// Up to MAX_FRAMES buffer pointers, passed by value in the kernel arguments
+// (no host-to-device copy of pointer tables).
+constexpr int MAX_FRAMES = 64;
+struct PtrList {
+    float *p[MAX_FRAMES];
+};
+
+struct ClNorm {
+    float in_mean[CREAL], in_inv[CREAL];    // x = (P - mean) * inv
+    float out_scale[CREAL];                 // correction = Pi(scale * y)
+    float ginv[16];                         // (Phi^T Phi)^-1, Phi = (1, vx, vy, |v|^2)
+    float vx[CREAL], vy[CREAL];
+};
+
+__device__ __forceinline__ u16 bf16_bits(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
+__device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Pi v = v - Phi G^-1 Phi^T v, in place on 25 values
+__device__ __forceinline__ void project(float (&v)[CREAL], const ClNorm &nm)
+{
+    float m[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        const float vx = nm.vx[k], vy = nm.vy[k];
+        m[0] += v[k];
+        m[1] += vx * v[k];
+        m[2] += vy * v[k];
+        m[3] += (vx * vx + vy * vy) * v[k];
+    }
+    float a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a[i] = nm.ginv[4 * i] * m[0] + nm.ginv[4 * i + 1] * m[1] + nm.ginv[4 * i + 2] * m[2] +
+               nm.ginv[4 * i + 3] * m[3];
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        const float vx = nm.vx[k], vy = nm.vy[k];
+        v[k] -= a[0] + a[1] * vx + a[2] * vy + a[3] * (vx * vx + vy * vy);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// population buffer (row layout (y*25 + k)*nx + x, FP32) -> normalised NHWC
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, ClNorm nm,
+                                                  u16 *__restrict__ x0)
+{
+    const int f = blockIdx.z;
+    const int y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const float *P = post.p[f];
+    uint32_t w[CH / 2];
+#pragma unroll
+    for (int c = 0; c < CH; c += 2) {
+        float a = 0.f, b = 0.f;
+        if (c < CREAL) a = (P[((size_t)y * CREAL + c) * nx + x] - nm.in_mean[c]) * nm.in_inv[c];
+        if (c + 1 < CREAL) b = (P[((size_t)y * CREAL + c + 1) * nx + x] - nm.in_mean[c + 1]) * nm.in_inv[c + 1];
+        w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(x0 + (((size_t)f * ny + y) * nx + x) * CH);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 periodic convolution as implicit GEMM on 32x32x16 bf16 MFMA.
+// MODE 0: forward hidden layer  out = bf16(relu(conv + bias))
+// MODE 1: forward last layer    out = f32(conv + bias)
+// MODE 2: input gradient        out = bf16(conv_mirrored(dz, W^T) * (act > 0))
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_cl_conv(const u16 *__restrict__ in, const u16 *__restrict__ wb,
+                                                 const float *__restrict__ bias,
+                                                 const u16 *__restrict__ act, void *__restrict__ out,
+                                                 int nx, int ny)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int x0 = (blockIdx.x * 4 + wv) * 32;       // first node of this wave
+    if (x0 >= nx) return;
+    const int row_i = l & 31, kh = l >> 5;            // A: node row_i, channels 8*kh..
+    const size_t fbase = (size_t)f * ny * nx;
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+        int dy = t / 3 - 1, dx = t % 3 - 1;
+        if (MODE == 2) {
+            dy = -dy;
+            dx = -dx;
+        }
+        int ys = y + dy;
+        ys += (ys < 0) ? ny : 0;
+        ys -= (ys >= ny) ? ny : 0;
+        int xs = x0 + row_i + dx;
+        xs += (xs < 0) ? nx : 0;
+        xs -= (xs >= nx) ? nx : 0;
+        const u16 *src = in + (fbase + (size_t)ys * nx + xs) * CH;
+        // B: column (output channel) l & 31, k = 8*kh.. within each half
+        const u16 *wt = wb + ((size_t)t * CH + (l & 31)) * CH;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(src + h * 16 + 8 * kh);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(wt + h * 16 + 8 * kh);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+    // D[i][j]: i = node 8*(r/4) + 4*(l/32) + r%4, j = channel l%32
+    const int j = l & 31;
+    const float bj = (MODE == 2) ? 0.f : bias[j];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
+        const size_t node = fbase + (size_t)y * nx + x0 + i;
+        float v = acc[r] + bj;
+        if (MODE == 0) {
+            reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(fmaxf(v, 0.f));
+        } else if (MODE == 1) {
+            reinterpret_cast<float *>(out)[node * CH + j] = v;
+        } else {
+            const float a = bf16_val(act[node * CH + j]);
+            reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(a > 0.f ? v : 0.f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[t][o][i] = sum_p dz[p][o] * a[p + d_t][i], db[o] = sum_p dz[p][o].
+// Block = WG_SEG nodes x WG_ROWS rows of one frame; wave w owns taps w, w+4, w+8.
+// LDS holds dz (channel-major, WG_SEG nodes) and the three input rows around y
+// (channel-major, WG_SEG + 2 nodes each).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, const u16 *__restrict__ dz,
+                                                  int nx, int ny, float *__restrict__ part)
+{
+    __shared__ u16 sdz[CH][WG_SEG + 8];
+    __shared__ u16 sa[3][CH][WG_SEG + 8];
+    const int f = blockIdx.z;
+    const int segs = nx / WG_SEG;
+    const int x0 = (blockIdx.x % segs) * WG_SEG;
+    const int y0 = (blockIdx.x / segs) * WG_ROWS;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const size_t fbase = (size_t)f * ny * nx;
+    f32x16 acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = f32x16{};
+    float bsum = 0.f;
+
+    for (int r = 0; r < WG_ROWS; ++r) {
+        const int y = y0 + r;
+        if (y >= ny) break;
+        __syncthreads();
+        // stage dz row: WG_SEG nodes x 32 channels, transposed
+        for (int e = threadIdx.x; e < WG_SEG * CH; e += 256) {
+            const int node = e / CH, c = e % CH;
+            sdz[c][node] = dz[(fbase + (size_t)y * nx + x0 + node) * CH + c];
+        }
+        // stage the three input rows y-1, y, y+1 at x0-1 .. x0+WG_SEG
+        for (int e = threadIdx.x; e < 3 * (WG_SEG + 2) * CH; e += 256) {
+            const int rr = e / ((WG_SEG + 2) * CH);
+            const int rem = e % ((WG_SEG + 2) * CH);
+            const int node = rem / CH, c = rem % CH;
+            int ys = y + rr - 1;
+            ys += (ys < 0) ? ny : 0;
+            ys -= (ys >= ny) ? ny : 0;
+            int xs = x0 + node - 1;
+            xs += (xs < 0) ? nx : 0;
+            xs -= (xs >= nx) ? nx : 0;
+            sa[rr][c][node] = a[(fbase + (size_t)ys * nx + xs) * CH + c];
+        }
+        __syncthreads();
+        if (wv == 0 && l < CH) {
+            for (int node = 0; node < WG_SEG; ++node) bsum += bf16_val(sdz[l][node]);
+        }
+        // A = dz^T (row o = l&31, k = nodes), B = a_t (col i = l&31, k = nodes)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int t = wv + 4 * q;
+            if (t >= TAPS) break;
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+            for (int kc = 0; kc < WG_SEG / 16; ++kc) {
+                const int n0 = kc * 16 + 8 * (l >> 5);
+                bf16x8 av, bv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    av[e] = __builtin_bit_cast(__bf16, sdz[l & 31][n0 + e]);
+                    bv[e] = __builtin_bit_cast(__bf16, sa[dy + 1][l & 31][n0 + e + dx + 1]);
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    // partials: [block][t][o][i] then [block][bias o]
+    const size_t nblk = (size_t)gridDim.x * gridDim.y * gridDim.z;
+    const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int t = wv + 4 * q;
+        if (t >= TAPS) break;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
+            part[blk * LAYER_W + ((size_t)t * CH + o) * CH + (l & 31)] = acc[q][r];
+        }
+    }
+    if (wv == 0 && l < CH) part[nblk * LAYER_W + blk * CH + l] = bsum;
+}
+
+// Sum the block partials in a fixed order into the flat gradient of one layer.
+__global__ __launch_bounds__(256) void k_cl_wgrad_reduce(const float *__restrict__ part, int nblk,
+                                                         float *__restrict__ grad)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= LAYER_P) return;
+    float s = 0.f;
+    if (i < LAYER_W) {
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * LAYER_W + i];
+    } else {
+        const int o = i - LAYER_W;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)nblk * LAYER_W + (size_t)b * CH + o];
+    }
+    grad[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Loss: r = Pi(s * y) - Pi(P_target - P), L = mean_nodes sum_k (r_k / s_k)^2,
+// dL/dy = (2 / N) s * Pi(r / s^2) -> bf16 NHWC (zero in the padding).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_loss(const float *__restrict__ y3, PtrList post,
+                                                 PtrList target, int nx, int ny, ClNorm nm, float inv_n,
+                                                 u16 *__restrict__ dy3, float *__restrict__ lpart)
+{
+    __shared__ float red[4];
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    float lsum = 0.f;
+    if (x < nx) {
+        const size_t node = ((size_t)f * ny + y) * nx + x;
+        float pr[CREAL], tg[CREAL];
+#pragma unroll
+        for (int k = 0; k < CREAL; ++k) {
+            pr[k] = y3[node * CH + k] * nm.out_scale[k];
+            const size_t e = ((size_t)y * CREAL + k) * nx + x;
+            tg[k] = target.p[f][e] - post.p[f][e];
+        }
+        project(pr, nm);
+        project(tg, nm);
+        float q[CREAL];
+#pragma unroll
+        for (int k = 0; k < CREAL; ++k) {
+            const float rk = pr[k] - tg[k];
+            const float is = 1.0f / nm.out_scale[k];
+            lsum += rk * is * rk * is;
+            q[k] = rk * is * is;
+        }
+        project(q, nm);
+        uint32_t w[CH / 2];
+#pragma unroll
+        for (int c = 0; c < CH; c += 2) {
+            const float a = c < CREAL ? 2.f * inv_n * nm.out_scale[c] * q[c] : 0.f;
+            const float b = c + 1 < CREAL ? 2.f * inv_n * nm.out_scale[c + 1] * q[c + 1] : 0.f;
+            w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(dy3 + node * CH);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        lpart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
+            (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Apply: P += Pi(s * y) where the correction is finite and every component is
+// within bound * s_k; otherwise the node keeps the plain post-collision
+// populations (fallback) and the skip counter is incremented.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_apply(const float *__restrict__ y3, PtrList post, int nx,
+                                                  int ny, ClNorm nm, float bound,
+                                                  unsigned *__restrict__ skipped)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const size_t node = ((size_t)f * ny + y) * nx + x;
+    float d[CREAL];
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) d[k] = y3[node * CH + k] * nm.out_scale[k];
+    project(d, nm);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) ok = ok && (fabsf(d[k]) <= bound * nm.out_scale[k]);
+    if (!ok) {
+        if (skipped) atomicAdd(skipped, 1u);
+        return;
+    }
+    float *P = post.p[f];
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) P[((size_t)y * CREAL + k) * nx + x] += d[k];
+}
+
+// FP32 parameters -> bf16 [t][o][i] (forward) and [t][i][o] (input gradient)
+__global__ __launch_bounds__(256) void k_cl_cast(const float *__restrict__ params, u16 *__restrict__ wf,
+                                                 u16 *__restrict__ wt)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= 3 * LAYER_W) return;
+    const int layer = e / LAYER_W, r = e % LAYER_W;
+    const int t = r / (CH * CH), o = (r / CH) % CH, i = r % CH;
+    const u16 h = bf16_bits(params[(size_t)layer * LAYER_P + r]);
+    wf[e] = h;
+    wt[(size_t)layer * LAYER_W + ((size_t)t * CH + i) * CH + o] = h;
+}
+
+__global__ __launch_bounds__(256) void k_cl_adam(float *__restrict__ p, const float *__restrict__ g,
+                                                 float *__restrict__ m, float *__restrict__ v, float lr,
+                                                 float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= NPARAM) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// Restriction: 4x4 block means of rho, rho u and E = rho (2 theta + |u|^2)
+// of FP64 fine fields -> coarse (rho, u, theta).
+__global__ __launch_bounds__(256) void k_restrict(const double *__restrict__ rho, const double *__restrict__ ux,
+                                                  const double *__restrict__ uy,
+                                                  const double *__restrict__ th, int fnx, int fny,
+                                                  int factor, double *__restrict__ crho,
+                                                  double *__restrict__ cux, double *__restrict__ cuy,
+                                                  double *__restrict__ cth)
+{
+    const int cnx = fnx / factor;
+    const int X = blockIdx.x * 256 + threadIdx.x, Y = blockIdx.y;
+    if (X >= cnx) return;
+    double r = 0, jx = 0, jy = 0, e = 0;
+    for (int dy = 0; dy < factor; ++dy)
+        for (int dx = 0; dx < factor; ++dx) {
+            const size_t n = (size_t)(Y * factor + dy) * fnx + X * factor + dx;
+            const double rr = rho[n], u = ux[n], w = uy[n];
+            r += rr;
+            jx += rr * u;
+            jy += rr * w;
+            e += rr * (2.0 * th[n] + u * u + w * w);
+        }
+    const double inv = 1.0 / r;
+    const double u = jx * inv, w = jy * inv;
+    const size_t c = (size_t)Y * cnx + X;
+    crho[c] = r / (factor * factor);
+    cux[c] = u;
+    cuy[c] = w;
+    cth[c] = 0.5 * (e * inv - u * u - w * w);
+}
+
+int ck(hipError_t e) { return e == hipSuccess ? PLBM_OK : PLBM_EHIP; }
+
+} // namespace
+
+struct plbm_closure {
+    int nx = 0, ny = 0, frames = 0;
+    ClNorm nm;
+    u16 *wf = nullptr, *wt = nullptr;          // bf16 weights
+    u16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr;
+    float *y3 = nullptr;
+    u16 *dy3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
+    float *part = nullptr;                     // weight-gradient partials
+    float *lpart = nullptr;                    // loss partials
+    int nwblk = 0, nlblk = 0;
+    int frames_in_fwd = 0;
+    const float *cast_from = nullptr;
+};
+
+namespace {
+
+int make_list(PtrList &l, const float *const *host, int n)
+{
+    std::memset(&l, 0, sizeof(l));
+    for (int i = 0; i < n; ++i) {
+        if (!host[i]) return PLBM_EINVAL;
+        l.p[i] = const_cast<float *>(host[i]);
+    }
+    return PLBM_OK;
+}
+
+int cast_weights(plbm_closure *c, const float *params, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cl_cast, dim3((3 * LAYER_W + 255) / 256), dim3(256), 0, st, params, c->wf, c->wt);
+    return ck(hipGetLastError());
+}
+
+} // namespace
+
+extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_closure **out)
+{
+    if (!coarse || !out || frames < 1 || frames > MAX_FRAMES) return PLBM_EINVAL;
+    *out = nullptr;
+    if (coarse->dim != 2 || coarse->storage != PLBM_F32) return PLBM_EUNSUPPORTED;
+    const int rc0 = plbm::validate(coarse);
+    if (rc0 != PLBM_OK) return rc0;
+    if (coarse->nx % WG_SEG != 0 || coarse->nx < WG_SEG) return PLBM_EUNSUPPORTED;
+    KParams kp;
+    const int rck = make_params(coarse, kp);
+    if (rck != PLBM_OK) return rck;
+    plbm_closure *c = new plbm_closure();
+    c->nx = coarse->nx;
+    c->ny = coarse->ny;
+    c->frames = frames;
+    std::memset(&c->nm, 0, sizeof(c->nm));
+    for (int k = 0; k < CREAL; ++k) {
+        c->nm.vx[k] = (float)coarse->v[k % 5];
+        c->nm.vy[k] = (float)coarse->v[k / 5];
+        c->nm.in_inv[k] = 1.f;
+        c->nm.out_scale[k] = 1.f;
+    }
+    // G = Phi^T Phi (4x4) and its inverse, in double
+    double G[4][4] = {{0}};
+    for (int k = 0; k < CREAL; ++k) {
+        const double vx = coarse->v[k % 5], vy = coarse->v[k / 5];
+        const double phi[4] = {1.0, vx, vy, vx * vx + vy * vy};
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) G[i][j] += phi[i] * phi[j];
+    }
+    double A[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) A[i][j] = j < 4 ? G[i][j] : (j - 4 == i ? 1.0 : 0.0);
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        for (int j = 0; j < 8; ++j) std::swap(A[col][j], A[piv][j]);
+        const double d = A[col][col];
+        if (d == 0.0) {
+            delete c;
+            return PLBM_ESINGULAR;
+        }
+        for (int j = 0; j < 8; ++j) A[col][j] /= d;
+        for (int r = 0; r < 4; ++r)
+            if (r != col) {
+                const double fct = A[r][col];
+                for (int j = 0; j < 8; ++j) A[r][j] -= fct * A[col][j];
+            }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) c->nm.ginv[4 * i + j] = (float)A[i][4 + j];
+
+    const size_t nodes = (size_t)frames * c->nx * c->ny;
+    c->nwblk = frames * ((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS));
+    c->nlblk = frames * c->ny * ((c->nx + 255) / 256);
+    bool ok = hipMalloc((void **)&c->wf, 3 * LAYER_W * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->wt, 3 * LAYER_W * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->x0, nodes * CH * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->a1, nodes * CH * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->a2, nodes * CH * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->y3, nodes * CH * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->dy3, nodes * CH * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->dz2, nodes * CH * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->dz1, nodes * CH * sizeof(u16)) == hipSuccess &&
+              hipMalloc((void **)&c->part, (size_t)c->nwblk * (LAYER_W + CH) * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->lpart, (size_t)c->nlblk * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        plbm_closure_destroy(c);
+        return PLBM_EHIP;
+    }
+    *out = c;
+    return PLBM_OK;
+}
+
+extern "C" int plbm_closure_destroy(plbm_closure *c)
+{
+    if (!c) return PLBM_EINVAL;
+    (void)hipDeviceSynchronize();
+    void *ptrs[] = {c->wf, c->wt, c->x0, c->a1, c->a2, c->y3, c->dy3, c->dz2, c->dz1, c->part,
+                    c->lpart};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete c;
+    return PLBM_OK;
+}
+
+extern "C" int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, const float *in_scale,
+                                     const float *out_scale)
+{
+    if (!c || !in_mean || !in_scale || !out_scale) return PLBM_EINVAL;
+    for (int k = 0; k < CREAL; ++k) {
+        if (!(in_scale[k] > 0.f) || !(out_scale[k] > 0.f) || !std::isfinite(in_mean[k]))
+            return PLBM_EINVAL;
+        c->nm.in_mean[k] = in_mean[k];
+        c->nm.in_inv[k] = 1.0f / in_scale[k];
+        c->nm.out_scale[k] = out_scale[k];
+    }
+    return PLBM_OK;
+}
+
+extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const float *const *post,
+                                    int frames, void *stream)
+{
+    if (!c || !params || !post || frames < 1 || frames > c->frames) return PLBM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    PtrList pl;
+    int rc = make_list(pl, post, frames);
+    if (rc != PLBM_OK) return rc;
+    (void)hipGetLastError();
+    rc = cast_weights(c, params, st);
+    if (rc != PLBM_OK) return rc;
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    const dim3 gc((c->nx / 32 + 3) / 4, c->ny, frames);
+    hipLaunchKernelGGL(k_cl_input, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, c->x0);
+    // bias of layer l: params + l * LAYER_P + LAYER_W
+    hipLaunchKernelGGL(k_cl_conv<0>, gc, dim3(256), 0, st, c->x0, c->wf, params + LAYER_W, nullptr, c->a1,
+                       c->nx, c->ny);
+    hipLaunchKernelGGL(k_cl_conv<0>, gc, dim3(256), 0, st, c->a1, c->wf + LAYER_W, params + LAYER_P + LAYER_W,
+                       nullptr, c->a2, c->nx, c->ny);
+    hipLaunchKernelGGL(k_cl_conv<1>, gc, dim3(256), 0, st, c->a2, c->wf + 2 * LAYER_W,
+                       params + 2 * LAYER_P + LAYER_W, nullptr, c->y3, c->nx, c->ny);
+    c->frames_in_fwd = frames;
+    return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const float *const *post,
+                                     const float *const *target, float *grads, double *loss,
+                                     void *stream)
+{
+    if (!c || !params || !post || !target || !grads || c->frames_in_fwd < 1) return PLBM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int frames = c->frames_in_fwd;
+    PtrList pl, tl;
+    int rc = make_list(pl, post, frames);
+    if (rc == PLBM_OK) rc = make_list(tl, target, frames);
+    if (rc != PLBM_OK) return rc;
+    (void)hipGetLastError();
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    const dim3 gc((c->nx / 32 + 3) / 4, c->ny, frames);
+    const dim3 gw((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS), 1, frames);
+    const int nwblk = (int)(gw.x * gw.z);
+    const float inv_n = 1.0f / ((float)frames * c->nx * c->ny);
+    hipLaunchKernelGGL(k_cl_loss, gn, dim3(256), 0, st, c->y3, pl, tl, c->nx, c->ny, c->nm, inv_n, c->dy3,
+                       c->lpart);
+    // layer 3: dW3 from a2 and dy3; dz2 = (W3^T dy3) * (a2 > 0)
+    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a2, c->dy3, c->nx, c->ny, c->part);
+    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
+                       grads + 2 * LAYER_P);
+    hipLaunchKernelGGL(k_cl_conv<2>, gc, dim3(256), 0, st, c->dy3, c->wt + 2 * LAYER_W, nullptr, c->a2,
+                       c->dz2, c->nx, c->ny);
+    // layer 2
+    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a1, c->dz2, c->nx, c->ny, c->part);
+    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
+                       grads + LAYER_P);
+    hipLaunchKernelGGL(k_cl_conv<2>, gc, dim3(256), 0, st, c->dz2, c->wt + LAYER_W, nullptr, c->a1, c->dz1,
+                       c->nx, c->ny);
+    // layer 1
+    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->x0, c->dz1, c->nx, c->ny, c->part);
+    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
+                       grads);
+    rc = ck(hipGetLastError());
+    if (rc != PLBM_OK || !loss) return rc;
+    const int nl = (int)(gn.x * gn.y * gn.z);
+    std::vector<float> h(nl);
+    rc = ck(hipMemcpyAsync(h.data(), c->lpart, nl * sizeof(float), hipMemcpyDeviceToHost, st));
+    if (rc == PLBM_OK) rc = ck(hipStreamSynchronize(st));
+    if (rc != PLBM_OK) return rc;
+    double s = 0.0;
+    for (float v : h) s += v;
+    *loss = s * inv_n;
+    return std::isfinite(*loss) ? PLBM_OK : PLBM_ENONFINITE;
+}
+
+extern "C" int plbm_closure_adam(plbm_closure *c, float *params, const float *grads, float *m, float *v,
+                                 int t, float lr, float b1, float b2, float eps, void *stream)
+{
+    if (!c || !params || !grads || !m || !v || t < 1) return PLBM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, t)));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_cl_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, st, params, grads, m, v, lr, b1,
+                       b2, eps, c1, c2);
+    return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_apply(plbm_closure *c, float *const *post, int frames, float bound,
+                                  unsigned *skipped, void *stream)
+{
+    if (!c || !post || frames < 1 || frames != c->frames_in_fwd || !(bound > 0.f)) return PLBM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    PtrList pl;
+    const int rc = make_list(pl, post, frames);
+    if (rc != PLBM_OK) return rc;
+    (void)hipGetLastError();
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    hipLaunchKernelGGL(k_cl_apply, gn, dim3(256), 0, st, c->y3, pl, c->nx, c->ny, c->nm, bound, skipped);
+    return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes)
+{
+    if (!c || !ptr) return PLBM_EINVAL;
+    const size_t nodes = (size_t)c->frames * c->nx * c->ny;
+    const void *p = nullptr;
+    size_t b = nodes * CH * sizeof(u16);
+    switch (which) {
+    case 0: p = c->x0; break;
+    case 1: p = c->a1; break;
+    case 2: p = c->a2; break;
+    case 3: p = c->y3; b = nodes * CH * sizeof(float); break;
+    case 4: p = c->dy3; break;
+    case 5: p = c->dz2; break;
+    case 6: p = c->dz1; break;
+    default: return PLBM_EINVAL;
+    }
+    *ptr = p;
+    if (bytes) *bytes = b;
+    return PLBM_OK;
+}
+
+extern "C" int plbm_restrict(const double *rho, const double *ux, const double *uy, const double *theta,
+                             int fnx, int fny, int factor, double *crho, double *cux, double *cuy,
+                             double *ctheta, void *stream)
+{
+    if (!rho || !ux || !uy || !theta || !crho || !cux || !cuy || !ctheta) return PLBM_EINVAL;
+    if (factor < 1 || fnx < factor || fny < factor || fnx % factor || fny % factor) return PLBM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const int cnx = fnx / factor, cny = fny / factor;
+    hipLaunchKernelGGL(k_restrict, dim3((cnx + 255) / 256, cny), dim3(256), 0, st, rho, ux, uy, theta, fnx,
+                       fny, factor, crho, cux, cuy, ctheta);
+    return ck(hipGetLastError());
+}
