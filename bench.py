@@ -59,6 +59,12 @@ def parse():
                     help="steps of the batching form (0 skips it)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batching form (for profilers)")
+    ap.add_argument("--closure-iters", type=int, default=2000,
+                    help="training iterations of the learned closure (0 skips it)")
+    ap.add_argument("--closure-train-seeds", type=int, default=200)
+    ap.add_argument("--closure-held-seeds", type=int, default=20)
+    ap.add_argument("--closure-only", action="store_true",
+                    help="run only the learned-closure experiment")
     return ap.parse_args()
 
 
@@ -185,6 +191,16 @@ def batch_form(steps, seed=0):
             "autotune_s": tune_s, "finite_sampled": finite}
 
 
+def closure_form(args):
+    """Learned closure: coarse 256^2 KH (FP32, omega viscosity-matched),
+    network trained on restricted 1024^2 runs of the training seeds, judged on
+    held-out seeds against the restricted fine run over 500 coarse steps."""
+    from paper_1402_5487_amd import closure_train
+    nt, nh = args.closure_train_seeds, args.closure_held_seeds
+    return closure_train.run(train_seeds=range(nt), held_seeds=range(200, 200 + nh),
+                             iters=args.closure_iters, log=log)
+
+
 def cpu_baseline(n, fields, steps):
     import oracle
     lat = oracle.Lattice(2, n, n, omega=1.8)
@@ -216,6 +232,9 @@ def main():
     if args.batch_only:
         print(json.dumps(batch_form(args.batch_steps)), flush=True)
         return
+    if args.closure_only:
+        print(json.dumps(closure_form(args)), flush=True)
+        return
 
     n = args.size
     fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80.0, theta=args.theta)
@@ -237,6 +256,10 @@ def main():
     if args.batch_steps > 0:
         log(f"batching form, {args.batch_steps} steps")
         batch = batch_form(args.batch_steps)
+    closure = None
+    if args.closure_iters > 0:
+        log("learned closure")
+        closure = closure_form(args)
 
     head = "f16dev" if "f16dev" in results else forms[0]
     h = results[head]
@@ -280,6 +303,7 @@ def main():
         "vs_fp64_speedup": round(h["mlups"] / results["f64"]["mlups"], 3)
         if "f64" in results else None,
         "batch": rnd(batch) if batch else None,
+        "closure": rnd(closure) if closure else None,
         "copy_gbs": round(copy_gbs, 1),
         "copy_ok": copy_ok,
         "kernel_sha256_16": kernel_hash(),

@@ -271,9 +271,11 @@ int plbm_batch_query(const plbm_batch *b, plbm_batch_info *info);
  * Learned closure: a 3-layer 3x3 convolutional network (25 -> 32 -> 32 -> 25
  * channels, ReLU, periodic padding; BF16 MFMA with FP32 accumulation) that
  * corrects a coarse FP32 D2Q25 lattice's post-collision populations P:
- *   P <- P + Pi(s * CNN((P - mean) / scale))
- * where Pi removes, node by node, the correction's mass, momentum and energy
- * (the collision invariants), so a corrected step still conserves them.
+ *   P <- P + s * Ph(CNN((P - mean) / scale))
+ * where Ph = I - B (B^T B)^-1 B^T with B = diag(s) Phi, Phi_k = (1, v_x,
+ * v_y, |v|^2): node by node it removes the correction's mass, momentum and
+ * energy (the collision invariants) orthogonally in the metric
+ * sum_k (x_k / s_k)^2, so a corrected step still conserves them.
  * Training targets come from restricted fine-lattice runs (plbm_restrict).
  * ------------------------------------------------------------------------ */
 typedef struct plbm_closure plbm_closure;      /* opaque, owns workspaces */
@@ -309,7 +311,7 @@ int plbm_closure_forward(plbm_closure *c, const float *params, const float *cons
 
 /*
  * plbm_closure_backward -- loss L = mean over nodes of
- * sum_k ((Pi(s y) - Pi(target - post))_k / s_k)^2 for the last forward pass
+ * |Ph (y - (target - post) / s)|^2 for the last forward pass
  * and its gradient with respect to `params`, written to `grads` (device,
  * PLBM_CNN_PARAMS floats).  target: host array of device pointers to the
  * desired post-collision buffers.  loss: NULL, or a host double receiving L
@@ -323,11 +325,11 @@ int plbm_closure_adam(plbm_closure *c, float *params, const float *grads, float 
                       int t, float lr, float b1, float b2, float eps, void *stream);
 
 /*
- * plbm_closure_apply -- add the projected correction of the last forward pass
- * to the same post buffers, in place.  Fallback: a node whose correction is
- * not finite or exceeds bound * s_k in any component keeps its plain
- * post-collision populations, and *skipped (device counter, nullable) is
- * incremented.
+ * plbm_closure_apply -- add the projected correction s * Ph y of the last
+ * forward pass to the same post buffers, in place.  Fallback: a node whose
+ * normalised correction Ph y is not finite or exceeds `bound` in magnitude in
+ * any component keeps its plain post-collision populations, and *skipped
+ * (device counter, nullable) is incremented.
  */
 int plbm_closure_apply(plbm_closure *c, float *const *post, int frames, float bound,
                        unsigned *skipped, void *stream);

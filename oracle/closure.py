@@ -9,11 +9,12 @@ plain, slow definition the GPU kernels are checked against:
       out[y, x, o] = b[o] + sum_{dy, dx in {-1, 0, 1}} sum_i
                      in[(y + dy) mod H, (x + dx) mod W, i] * w[dy + 1, dx + 1, i, o]
   network: conv(25 -> 32), ReLU, conv(32 -> 32), ReLU, conv(32 -> 25)
-  projection: per node, remove from a 25-vector its components along the
-      conserved moments phi = (1, v_x, v_y, |v|^2) of the D2Q25 velocities,
-      Pi = I - Phi (Phi^T Phi)^-1 Phi^T (Eq. srt conserves exactly these, so a
-      projected correction leaves mass, momentum and energy unchanged)
-  loss: mean over nodes of sum_k ((Pi(s * y) - Pi(t))_k / s_k)^2
+  projection (normalised coordinates, output scales s): with
+      B = diag(s) Phi, Phi_k = (1, v_x, v_y, |v|^2) of the D2Q25 velocities,
+      Ph = I - B (B^T B)^-1 B^T, so the physical correction s * (Ph y) has
+      zero mass, momentum and energy (the invariants of Eq. srt); it is the
+      closest such vector in the metric sum_k (x_k / s_k)^2
+  loss: mean over nodes of |Ph (y - t / s)|^2, t the target correction
   Adam (Kingma & Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
       p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
   restriction: 4 x 4 block means of rho, rho u and sum f |v|^2.
@@ -30,11 +31,18 @@ def velocities_2d():
     return np.array([[V5[k % 5], V5[k // 5]] for k in range(25)])
 
 
-def projection():
-    """Pi (25 x 25) onto the complement of span{1, v_x, v_y, |v|^2}."""
+def conserved_basis():
+    """Phi (25 x 4): 1, v_x, v_y, |v|^2 at each velocity."""
     v = velocities_2d()
-    phi = np.stack([np.ones(25), v[:, 0], v[:, 1], (v ** 2).sum(1)], axis=1)
-    return np.eye(25) - phi @ np.linalg.solve(phi.T @ phi, phi.T)
+    return np.stack([np.ones(25), v[:, 0], v[:, 1], (v ** 2).sum(1)], axis=1)
+
+
+def projection(scale=None):
+    """Ph (25 x 25) in normalised coordinates for output scales `scale`
+    (all ones: the Euclidean projection)."""
+    s = np.ones(25) if scale is None else np.asarray(scale, dtype=np.float64)
+    B = s[:, None] * conserved_basis()
+    return np.eye(25) - B @ np.linalg.solve(B.T @ B, B.T)
 
 
 def conv3x3(x, w, b):
@@ -84,15 +92,15 @@ def backward(params, cache, dy):
 
 
 def loss_and_grad(y, target, scale):
-    """Projected, scale-weighted squared error and its gradient w.r.t. y.
-    y: (H, W, 25) network output (normalised units); target: (H, W, 25)
-    correction in physical units; scale: (25,) s_k."""
-    P = projection()
+    """Projected squared error in normalised units and its gradient w.r.t. y.
+    y: (H, W, 25) network output; target: (H, W, 25) correction in physical
+    units; scale: (25,) s_k."""
     s = np.asarray(scale, dtype=np.float64)
-    r = (y * s) @ P.T - target @ P.T                  # Pi(s y) - Pi(t)
+    P = projection(s)
+    r = (y - target / s) @ P.T
     n = y.shape[0] * y.shape[1]
-    loss = ((r / s) ** 2).sum() / n
-    dy = ((r / s ** 2) @ P) * s * 2.0 / n             # Pi symmetric
+    loss = (r ** 2).sum() / n
+    dy = (r @ P) * 2.0 / n
     return loss, dy
 
 

@@ -161,3 +161,59 @@ class Experiment:
         finite = all(math.isfinite(x) for x in out["closure"])
         out["finite"] = finite
         return out
+
+
+def forward_rate(ex, reps=20):
+    """Inference throughput of the network on one batch: algorithmic FLOPs
+    (2 * 9 * (25*32 + 32*32 + 32*25) per node) over the measured time."""
+    posts = [f[0] for f in ex.frames[:ex.batch]]
+    ex.net.forward(ex.params, posts)
+    torch.cuda.synchronize(ex.device)
+    st = torch.cuda.current_stream(ex.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ex.net.forward(ex.params, posts)
+    e1.record(st)
+    torch.cuda.synchronize(ex.device)
+    ms = e0.elapsed_time(e1) / reps
+    nodes = ex.batch * ex.nc * ex.nc
+    flops = 2 * 9 * (25 * 32 + 32 * 32 + 32 * 25) * nodes
+    return ms, flops / (ms * 1e-3) / 1e12
+
+
+def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 220),
+        per_seed=10, horizon=500, iters=2000, batch=8, lr=1e-3, judge_steps=500,
+        judge_every=50, log=None):
+    """The full learned-closure experiment: generate, train, judge."""
+    import time
+    say = log or (lambda msg: None)
+    ex = Experiment(n_coarse=n_coarse, factor=factor, batch=batch)
+    t0 = time.perf_counter()
+    ex.generate(train_seeds, per_seed, horizon)
+    gen_s = time.perf_counter() - t0
+    say(f"closure: {len(ex.frames)} frames in {gen_s:.1f} s")
+    ex.fit_norm()
+    t0 = time.perf_counter()
+    hist = ex.train(iters, lr=lr, log_every=max(1, iters // 10))
+    train_s = time.perf_counter() - t0
+    say(f"closure: trained {iters} iterations in {train_s:.1f} s, loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g}")
+    fwd_ms, fwd_tflops = forward_rate(ex)
+    judged = []
+    for s in held_seeds:
+        judged.append(ex.judge(s, judge_steps, judge_every))
+    plain = [sum(j["plain"][i] for j in judged) / len(judged) for i in range(3)]
+    corr = [sum(j["closure"][i] for j in judged) / len(judged) for i in range(3)]
+    return {"coarse": n_coarse, "fine": n_coarse * factor, "omega_c": ex.omega_c,
+            "train_seeds": len(list(train_seeds)), "held_out_seeds": len(judged),
+            "frames": len(ex.frames), "iters": iters, "batch": batch,
+            "loss_first": hist[0][1], "loss_last": hist[-1][1], "gen_s": gen_s,
+            "train_s": train_s, "ms_per_iter": 1e3 * train_s / iters,
+            "forward_ms_per_batch": fwd_ms, "forward_tflops": fwd_tflops,
+            "judge_steps": judge_steps,
+            "rel_l2_plain": {"rho": plain[0], "u": plain[1], "theta": plain[2]},
+            "rel_l2_closure": {"rho": corr[0], "u": corr[1], "theta": corr[2]},
+            "gain": {"rho": plain[0] / corr[0], "u": plain[1] / corr[1],
+                     "theta": plain[2] / corr[2]},
+            "skipped_nodes": sum(j["skipped_nodes"] for j in judged),
+            "finite": all(j["finite"] for j in judged)}

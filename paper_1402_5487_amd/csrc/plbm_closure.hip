@@ -19,7 +19,8 @@
 //    partials are summed in a fixed order (deterministic).
 //  * Loss, projection and apply are per-node kernels: the projection removes
 //    the correction's mass, momentum and energy (the invariants of the
-//    collision), so an applied correction conserves them exactly.
+//    collision), orthogonally in the metric of the output scales, so an
+//    applied correction conserves them exactly.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -54,27 +55,33 @@ struct PtrList {
     float *p[MAX_FRAMES];
 };
 
+// Normalisation and projection.  With D = diag(s) (output scales) and
+// Phi = (1, vx, vy, |v|^2), B = D Phi and G = B^T B, the projection in
+// normalised coordinates is Ph = I - B G^-1 B^T: symmetric, idempotent, and
+// the physical correction D Ph y has zero mass, momentum and energy.  It is
+// the orthogonal projection in the metric sum_k (x_k / s_k)^2, so each
+// population absorbs a share proportional to its own scale.
 struct ClNorm {
     float in_mean[CREAL], in_inv[CREAL];    // x = (P - mean) * inv
-    float out_scale[CREAL];                 // correction = Pi(scale * y)
-    float ginv[16];                         // (Phi^T Phi)^-1, Phi = (1, vx, vy, |v|^2)
+    float out_scale[CREAL];                 // s_k
+    float ginv[16];                         // G^-1
     float vx[CREAL], vy[CREAL];
 };
 
 __device__ __forceinline__ u16 bf16_bits(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 __device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Pi v = v - Phi G^-1 Phi^T v, in place on 25 values
+// v <- Ph v = v - B G^-1 B^T v (normalised coordinates), in place
 __device__ __forceinline__ void project(float (&v)[CREAL], const ClNorm &nm)
 {
     float m[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < CREAL; ++k) {
-        const float vx = nm.vx[k], vy = nm.vy[k];
-        m[0] += v[k];
-        m[1] += vx * v[k];
-        m[2] += vy * v[k];
-        m[3] += (vx * vx + vy * vy) * v[k];
+        const float vx = nm.vx[k], vy = nm.vy[k], sv = nm.out_scale[k] * v[k];
+        m[0] += sv;
+        m[1] += vx * sv;
+        m[2] += vy * sv;
+        m[3] += (vx * vx + vy * vy) * sv;
     }
     float a[4];
 #pragma unroll
@@ -84,7 +91,7 @@ __device__ __forceinline__ void project(float (&v)[CREAL], const ClNorm &nm)
 #pragma unroll
     for (int k = 0; k < CREAL; ++k) {
         const float vx = nm.vx[k], vy = nm.vy[k];
-        v[k] -= a[0] + a[1] * vx + a[2] * vy + a[3] * (vx * vx + vy * vy);
+        v[k] -= nm.out_scale[k] * (a[0] + a[1] * vx + a[2] * vy + a[3] * (vx * vx + vy * vy));
     }
 }
 
@@ -273,8 +280,9 @@ __global__ __launch_bounds__(256) void k_cl_wgrad_reduce(const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Loss: r = Pi(s * y) - Pi(P_target - P), L = mean_nodes sum_k (r_k / s_k)^2,
-// dL/dy = (2 / N) s * Pi(r / s^2) -> bf16 NHWC (zero in the padding).
+// Loss, in normalised coordinates: r = Ph (y - (P_target - P) / s),
+// L = mean over nodes of |r|^2, dL/dy = (2 / N) r (Ph symmetric idempotent)
+// -> bf16 NHWC (zero in the padding).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_cl_loss(const float *__restrict__ y3, PtrList post,
                                                  PtrList target, int nx, int ny, ClNorm nm, float inv_n,
@@ -286,29 +294,20 @@ __global__ __launch_bounds__(256) void k_cl_loss(const float *__restrict__ y3, P
     float lsum = 0.f;
     if (x < nx) {
         const size_t node = ((size_t)f * ny + y) * nx + x;
-        float pr[CREAL], tg[CREAL];
+        float r[CREAL];
 #pragma unroll
         for (int k = 0; k < CREAL; ++k) {
-            pr[k] = y3[node * CH + k] * nm.out_scale[k];
             const size_t e = ((size_t)y * CREAL + k) * nx + x;
-            tg[k] = target.p[f][e] - post.p[f][e];
+            r[k] = y3[node * CH + k] - (target.p[f][e] - post.p[f][e]) / nm.out_scale[k];
         }
-        project(pr, nm);
-        project(tg, nm);
-        float q[CREAL];
+        project(r, nm);
 #pragma unroll
-        for (int k = 0; k < CREAL; ++k) {
-            const float rk = pr[k] - tg[k];
-            const float is = 1.0f / nm.out_scale[k];
-            lsum += rk * is * rk * is;
-            q[k] = rk * is * is;
-        }
-        project(q, nm);
+        for (int k = 0; k < CREAL; ++k) lsum += r[k] * r[k];
         uint32_t w[CH / 2];
 #pragma unroll
         for (int c = 0; c < CH; c += 2) {
-            const float a = c < CREAL ? 2.f * inv_n * nm.out_scale[c] * q[c] : 0.f;
-            const float b = c + 1 < CREAL ? 2.f * inv_n * nm.out_scale[c + 1] * q[c + 1] : 0.f;
+            const float a = c < CREAL ? 2.f * inv_n * r[c] : 0.f;
+            const float b = c + 1 < CREAL ? 2.f * inv_n * r[c + 1] : 0.f;
             w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
         }
         uint4 *dst = reinterpret_cast<uint4 *>(dy3 + node * CH);
@@ -325,9 +324,9 @@ __global__ __launch_bounds__(256) void k_cl_loss(const float *__restrict__ y3, P
 }
 
 // ---------------------------------------------------------------------------
-// Apply: P += Pi(s * y) where the correction is finite and every component is
-// within bound * s_k; otherwise the node keeps the plain post-collision
-// populations (fallback) and the skip counter is incremented.
+// Apply: P += s * Ph y where the correction is finite and every normalised
+// component |Ph y|_k is within bound; otherwise the node keeps the plain
+// post-collision populations (fallback) and the skip counter is incremented.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_cl_apply(const float *__restrict__ y3, PtrList post, int nx,
                                                   int ny, ClNorm nm, float bound,
@@ -339,18 +338,18 @@ __global__ __launch_bounds__(256) void k_cl_apply(const float *__restrict__ y3, 
     const size_t node = ((size_t)f * ny + y) * nx + x;
     float d[CREAL];
 #pragma unroll
-    for (int k = 0; k < CREAL; ++k) d[k] = y3[node * CH + k] * nm.out_scale[k];
+    for (int k = 0; k < CREAL; ++k) d[k] = y3[node * CH + k];
     project(d, nm);
     bool ok = true;
 #pragma unroll
-    for (int k = 0; k < CREAL; ++k) ok = ok && (fabsf(d[k]) <= bound * nm.out_scale[k]);
+    for (int k = 0; k < CREAL; ++k) ok = ok && (fabsf(d[k]) <= bound);
     if (!ok) {
         if (skipped) atomicAdd(skipped, 1u);
         return;
     }
     float *P = post.p[f];
 #pragma unroll
-    for (int k = 0; k < CREAL; ++k) P[((size_t)y * CREAL + k) * nx + x] += d[k];
+    for (int k = 0; k < CREAL; ++k) P[((size_t)y * CREAL + k) * nx + x] += nm.out_scale[k] * d[k];
 }
 
 // FP32 parameters -> bf16 [t][o][i] (forward) and [t][i][o] (input gradient)
@@ -431,6 +430,37 @@ struct plbm_closure {
 
 namespace {
 
+// G = sum_k s_k^2 phi_k phi_k^T and its inverse (double, Gauss-Jordan)
+int set_projection(ClNorm &nm)
+{
+    double G[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) G[i][j] = (j - 4 == i) ? 1.0 : 0.0;
+    for (int k = 0; k < CREAL; ++k) {
+        const double vx = nm.vx[k], vy = nm.vy[k], s2 = (double)nm.out_scale[k] * nm.out_scale[k];
+        const double phi[4] = {1.0, vx, vy, vx * vx + vy * vy};
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) G[i][j] += s2 * phi[i] * phi[j];
+    }
+    for (int col = 0; col < 4; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (std::fabs(G[r][col]) > std::fabs(G[piv][col])) piv = r;
+        for (int j = 0; j < 8; ++j) std::swap(G[col][j], G[piv][j]);
+        const double d = G[col][col];
+        if (!(std::fabs(d) > 0.0)) return PLBM_ESINGULAR;
+        for (int j = 0; j < 8; ++j) G[col][j] /= d;
+        for (int r = 0; r < 4; ++r)
+            if (r != col) {
+                const double fct = G[r][col];
+                for (int j = 0; j < 8; ++j) G[r][j] -= fct * G[col][j];
+            }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) nm.ginv[4 * i + j] = (float)G[i][4 + j];
+    return PLBM_OK;
+}
+
 int make_list(PtrList &l, const float *const *host, int n)
 {
     std::memset(&l, 0, sizeof(l));
@@ -471,36 +501,10 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
         c->nm.in_inv[k] = 1.f;
         c->nm.out_scale[k] = 1.f;
     }
-    // G = Phi^T Phi (4x4) and its inverse, in double
-    double G[4][4] = {{0}};
-    for (int k = 0; k < CREAL; ++k) {
-        const double vx = coarse->v[k % 5], vy = coarse->v[k / 5];
-        const double phi[4] = {1.0, vx, vy, vx * vx + vy * vy};
-        for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) G[i][j] += phi[i] * phi[j];
+    if (set_projection(c->nm) != PLBM_OK) {
+        delete c;
+        return PLBM_ESINGULAR;
     }
-    double A[4][8];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 8; ++j) A[i][j] = j < 4 ? G[i][j] : (j - 4 == i ? 1.0 : 0.0);
-    for (int col = 0; col < 4; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < 4; ++r)
-            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
-        for (int j = 0; j < 8; ++j) std::swap(A[col][j], A[piv][j]);
-        const double d = A[col][col];
-        if (d == 0.0) {
-            delete c;
-            return PLBM_ESINGULAR;
-        }
-        for (int j = 0; j < 8; ++j) A[col][j] /= d;
-        for (int r = 0; r < 4; ++r)
-            if (r != col) {
-                const double fct = A[r][col];
-                for (int j = 0; j < 8; ++j) A[r][j] -= fct * A[col][j];
-            }
-    }
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) c->nm.ginv[4 * i + j] = (float)A[i][4 + j];
 
     const size_t nodes = (size_t)frames * c->nx * c->ny;
     c->nwblk = frames * ((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS));
@@ -540,13 +544,18 @@ extern "C" int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, cons
                                      const float *out_scale)
 {
     if (!c || !in_mean || !in_scale || !out_scale) return PLBM_EINVAL;
+    ClNorm nm = c->nm;
     for (int k = 0; k < CREAL; ++k) {
-        if (!(in_scale[k] > 0.f) || !(out_scale[k] > 0.f) || !std::isfinite(in_mean[k]))
+        if (!(in_scale[k] > 0.f) || !(out_scale[k] > 0.f) || !std::isfinite(in_mean[k]) ||
+            !std::isfinite(in_scale[k]) || !std::isfinite(out_scale[k]))
             return PLBM_EINVAL;
-        c->nm.in_mean[k] = in_mean[k];
-        c->nm.in_inv[k] = 1.0f / in_scale[k];
-        c->nm.out_scale[k] = out_scale[k];
+        nm.in_mean[k] = in_mean[k];
+        nm.in_inv[k] = 1.0f / in_scale[k];
+        nm.out_scale[k] = out_scale[k];
     }
+    const int rc = set_projection(nm);
+    if (rc != PLBM_OK) return rc;
+    c->nm = nm;
     return PLBM_OK;
 }
 

@@ -166,7 +166,7 @@ def test_apply_and_fallback(setup):
     posts = [p.clone() for p in setup["posts"]]
     net.forward(setup["params"], posts)
     y = np.stack([setup["acts"][3][f][..., :25] for f in range(FRAMES)])
-    corr = (y * setup["oscale"]) @ ocl.projection().T
+    corr = (y @ ocl.projection(setup["oscale"]).T) * setup["oscale"]
     skipped = torch.zeros(1, dtype=torch.int32, device="cuda")
     net.apply(posts, bound=1e30, skipped=skipped)
     got = np.stack([_nodes(p) for p in posts])

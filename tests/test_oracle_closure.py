@@ -72,14 +72,22 @@ def test_network_backward_matches_finite_differences():
         assert np.abs(gb - _num_grad(f, b)).max() < 1e-5
 
 
-def test_projection_properties():
-    P = cl.projection()
-    v = cl.velocities_2d()
-    phi = np.stack([np.ones(25), v[:, 0], v[:, 1], (v ** 2).sum(1)], axis=1)
-    assert np.abs(P @ P - P).max() < 1e-13
-    assert np.abs(P - P.T).max() < 1e-13
-    assert np.abs(phi.T @ P).max() < 1e-12          # removes mass, momentum, energy
+@pytest.mark.parametrize("scaled", [False, True])
+def test_projection_properties(scaled):
+    s = np.random.default_rng(3).uniform(1e-6, 1.0, 25) if scaled else np.ones(25)
+    P = cl.projection(s)
+    phi = cl.conserved_basis()
+    assert np.abs(P @ P - P).max() < 1e-12
+    assert np.abs(P - P.T).max() < 1e-12
+    # the physical correction s * (P y) has zero mass, momentum and energy
+    y = np.random.default_rng(4).standard_normal(25)
+    assert np.abs(phi.T @ (s * (P @ y))).max() < 1e-12 * np.abs(s * y).max() * 100
     assert round(np.trace(P)) == 21
+    # closest conserving vector in the metric sum (x/s)^2: P y - y is
+    # orthogonal to every admissible direction
+    q = np.random.default_rng(5).standard_normal(25)
+    adm = s * (P @ q)
+    assert abs(((P @ y - y) * (adm / s)).sum()) < 1e-10
 
 
 def test_loss_gradient_matches_finite_differences():
@@ -92,14 +100,14 @@ def test_loss_gradient_matches_finite_differences():
     assert np.abs(g - num).max() < 1e-6
 
 
-def test_loss_vanishes_on_conserved_directions():
-    """A target made only of mass/momentum/energy components is invisible to
-    the projected loss."""
-    v = cl.velocities_2d()
-    phi = np.stack([np.ones(25), v[:, 0], v[:, 1], (v ** 2).sum(1)], axis=1)
-    t = (np.random.default_rng(1).standard_normal((2, 2, 4)) @ phi.T)
-    loss, _ = cl.loss_and_grad(np.zeros((2, 2, 25)), t, np.ones(25))
-    assert loss < 1e-24
+def test_loss_ignores_what_no_admissible_correction_can_reach():
+    """The loss compares with the closest admissible (moment-free) correction
+    in the metric sum (x/s)^2; a target in the removed directions
+    s^2 * (Phi a) has the zero correction as its closest point."""
+    s = np.random.default_rng(2).uniform(0.01, 1.0, 25)
+    t = (np.random.default_rng(1).standard_normal((2, 2, 4)) @ cl.conserved_basis().T) * s ** 2
+    loss, _ = cl.loss_and_grad(np.zeros((2, 2, 25)), t, s)
+    assert loss < 1e-22
 
 
 def test_adam_first_step_is_lr_times_sign():
