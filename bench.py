@@ -30,14 +30,20 @@ sys.path.insert(0, ROOT)
 METRIC = ("MLUPS and % of HBM roofline, D2Q25 thermal KH 4096², "
           "vs plain FP64 step at stated err")
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1402_5487_amd", "csrc", "plbm_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1402_5487_amd", "csrc", n)
+              for n in ("plbm_kernels.hip", "plbm_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_kh4096_traffic.json")
 COMPUTE_DTYPE = {"f64": "f64", "f32": "f32", "f16dev": "f32", "bf16dev": "f32"}
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the step kernel's sources: stored HBM counter totals are used
+    only while it matches."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -61,8 +67,8 @@ def parse():
                     help="run only the batching form (for profilers)")
     ap.add_argument("--closure-iters", type=int, default=2000,
                     help="training iterations of the learned closure (0 skips it)")
-    ap.add_argument("--closure-train-seeds", type=int, default=200)
-    ap.add_argument("--closure-held-seeds", type=int, default=20)
+    ap.add_argument("--closure-train-seeds", type=int, default=100)
+    ap.add_argument("--closure-held-seeds", type=int, default=10)
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure experiment")
     return ap.parse_args()
@@ -192,7 +198,7 @@ def batch_form(steps, seed=0):
 
 
 def closure_form(args):
-    """Learned closure: coarse 256^2 KH (FP32, omega viscosity-matched),
+    """Learned closure: coarse 256^2 KH (FP64 populations, omega viscosity-matched),
     network trained on restricted 1024^2 runs of the training seeds, judged on
     held-out seeds against the restricted fine run over 500 coarse steps."""
     from paper_1402_5487_amd import closure_train

@@ -270,13 +270,15 @@ int plbm_batch_query(const plbm_batch *b, plbm_batch_info *info);
 /* ------------------------------------------------------------------------
  * Learned closure: a 3-layer 3x3 convolutional network (25 -> 32 -> 32 -> 25
  * channels, ReLU, periodic padding; BF16 MFMA with FP32 accumulation) that
- * corrects a coarse FP32 D2Q25 lattice's post-collision populations P:
- *   P <- P + s * Ph(CNN((P - mean) / scale))
- * where Ph = I - B (B^T B)^-1 B^T with B = diag(s) Phi, Phi_k = (1, v_x,
- * v_y, |v|^2): node by node it removes the correction's mass, momentum and
- * energy (the collision invariants) orthogonally in the metric
- * sum_k (x_k / s_k)^2, so a corrected step still conserves them.
- * Training targets come from restricted fine-lattice runs (plbm_restrict).
+ * corrects a coarse D2Q25 lattice (FP32 or FP64 storage) after its
+ * collide-and-stream step (Eq. srt).  Its output y, normalised by scales s,
+ * becomes c = s * Ph y with Ph = I - B (B^T B)^-1 B^T, B = diag(s) Phi,
+ * Phi_k = (1, v_x, v_y, |v|^2): node by node c carries no mass, momentum or
+ * energy (the collision invariants), so streamed it only moves them between
+ * nodes and the totals are conserved exactly.
+ * Training compares, after the next streaming, the conserved densities the
+ * correction adds with the one-step error of the plain coarse step against
+ * restricted fine-lattice runs (plbm_restrict, plbm_closure_target).
  * ------------------------------------------------------------------------ */
 typedef struct plbm_closure plbm_closure;      /* opaque, owns workspaces */
 
@@ -289,55 +291,86 @@ typedef struct plbm_closure plbm_closure;      /* opaque, owns workspaces */
 
 /*
  * plbm_closure_create -- workspaces for up to `frames` coarse lattices of
- * the shape of *coarse (dim 2, FP32 storage, nx a multiple of 64) processed
- * together.  Synchronous.  Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_EHIP.
+ * the shape of *coarse (dim 2, FP32 or FP64 storage, nx a multiple of 64,
+ * whole-node velocities smaller than nx and ny) processed together.
+ * Synchronous.  Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_EHIP.
  */
 int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_closure **out);
 int plbm_closure_destroy(plbm_closure *c);
 
-/* Normalisation (host arrays of 25): network input (P_k - in_mean[k]) /
- * in_scale[k]; correction s_k * y_k with s_k = out_scale[k]. */
+/* Normalisation (host arrays): network input (P_k - in_mean[k]) /
+ * in_scale[k] and correction s_k * y_k with s_k = out_scale[k] (25 each);
+ * moment_scale[4] = sigma_j of the loss (weights 1 / sigma_j^2 for rho,
+ * j_x, j_y, E).  All must be finite, scales positive. */
 int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, const float *in_scale,
-                          const float *out_scale);
+                          const float *out_scale, const float *moment_scale);
 
 /*
  * plbm_closure_forward -- run the network on `frames` post-collision buffers
  * (post: host array of device pointers, each a population buffer of the
- * coarse lattice) with parameters `params` (device, PLBM_CNN_PARAMS floats).
- * Keeps the activations for plbm_closure_backward / plbm_closure_apply.
+ * coarse lattice in its storage type) with parameters `params` (device,
+ * PLBM_CNN_PARAMS floats).  Keeps the activations for plbm_closure_backward
+ * and plbm_closure_apply.
  */
-int plbm_closure_forward(plbm_closure *c, const float *params, const float *const *post,
+int plbm_closure_forward(plbm_closure *c, const float *params, const void *const *post,
                          int frames, void *stream);
 
 /*
- * plbm_closure_backward -- loss L = mean over nodes of
- * |Ph (y - (target - post) / s)|^2 for the last forward pass
- * and its gradient with respect to `params`, written to `grads` (device,
- * PLBM_CNN_PARAMS floats).  target: host array of device pointers to the
- * desired post-collision buffers.  loss: NULL, or a host double receiving L
- * (synchronises `stream`; PLBM_ENONFINITE if not finite).
+ * plbm_closure_backward -- moment-form loss of the last forward pass and its
+ * gradient with respect to `params`, written to `grads` (device,
+ * PLBM_CNN_PARAMS floats).  With c = s * Ph y and m(x) = sum_k Phi_k
+ * (c_k(x - v_k) - c_k(x)) (the conserved densities the correction brings to
+ * node x after streaming, periodic, in flux form so their totals vanish),
+ *   L = mean over nodes of [sum_j (m_j - d_j)^2 / sigma_j^2 + reg |Ph y|^2];
+ * the moments fix 4 of a node's 21 free correction components and the
+ * minimum-norm weight reg >= 0 selects the smallest correction.
+ * target: host array of device pointers, one per frame, to d as four FP32
+ * planes [j][y][x] (rho, j_x, j_y, E), e.g. from plbm_closure_target.
+ * loss: NULL, or a host double receiving L (synchronises `stream`;
+ * PLBM_ENONFINITE if not finite).
  */
-int plbm_closure_backward(plbm_closure *c, const float *params, const float *const *post,
-                          const float *const *target, float *grads, double *loss, void *stream);
+int plbm_closure_backward(plbm_closure *c, const float *params, const float *const *target,
+                          float reg, float *grads, double *loss, void *stream);
 
 /* One Adam step (step count t >= 1) on device arrays of PLBM_CNN_PARAMS. */
 int plbm_closure_adam(plbm_closure *c, float *params, const float *grads, float *m, float *v,
                       int t, float lr, float b1, float b2, float eps, void *stream);
 
 /*
- * plbm_closure_apply -- add the projected correction s * Ph y of the last
- * forward pass to the same post buffers, in place.  Fallback: a node whose
- * normalised correction Ph y is not finite or exceeds `bound` in magnitude in
- * any component keeps its plain post-collision populations, and *skipped
- * (device counter, nullable) is incremented.
+ * plbm_closure_apply -- give the last forward pass's correction to the same
+ * post buffers, in place, in their storage type.  The correction c = s * Ph y
+ * moves the conserved densities g(x) = sum_k Phi_k (c_k(x - v_k) - c_k(x)) between
+ * nodes; apply hands them to the next step as a shift of the equilibrium,
+ *   f <- f + f_eq(m + g) - f_eq(m)   (f = the pulled populations, m their
+ *                                     moments; stored at x - v_k),
+ * so each node's mass, momentum and energy become m + g exactly and its
+ * non-equilibrium part is the plain step's.  Fallback: a node whose
+ * normalised correction Ph y is not finite or exceeds `bound` in magnitude
+ * in any component contributes nothing, and *skipped (device counter,
+ * nullable) is incremented; a node whose shifted density or temperature
+ * would not be positive keeps its populations.  Asynchronous.
  */
-int plbm_closure_apply(plbm_closure *c, float *const *post, int frames, float bound,
+int plbm_closure_apply(plbm_closure *c, void *const *post, int frames, float bound,
                        unsigned *skipped, void *stream);
 
-/* Device pointer and size of an internal activation (for tests):
+/* Device pointer and size of an internal buffer (for tests):
  * 0 input, 1 layer-1 output, 2 layer-2 output (bf16 NHWC x 32), 3 network
- * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs. */
+ * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs,
+ * 7 the physical correction c (FP32 planes [frame][k][y][x]),
+ * 8 dL/dm (FP32 planes [frame][j][y][x]), 9 the equilibrium shift of the
+ * last apply (FP64 planes [frame][k][y][x], population k of node x). */
 int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes);
+
+/*
+ * plbm_closure_target -- the loss target of one frame: the one-step change
+ * of the conserved densities cons = (rho, rho u_x, rho u_y, rho (2 theta +
+ * |u|^2)) of the truth minus that of the plain coarse step,
+ *   d = (cons(T1) - cons(T0)) - (cons(M1) - cons(M0)),
+ * computed in FP64 and rounded once.  fields: host array of 16 device FP64
+ * pointers, (rho, u_x, u_y, theta) of T0, T1, M0, M1 in that order, each
+ * `nodes` long; out: device FP32, four planes of `nodes`.  Asynchronous.
+ */
+int plbm_closure_target(const double *const *fields, size_t nodes, float *out, void *stream);
 
 /*
  * plbm_restrict -- block means over factor x factor fine nodes of rho,

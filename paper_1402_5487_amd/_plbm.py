@@ -223,9 +223,9 @@ def _setup_closure(lib):
     F = ctypes.POINTER(ctypes.c_float)
     lib.plbm_closure_create.argtypes = [P, ctypes.c_int, ctypes.POINTER(vp)]
     lib.plbm_closure_destroy.argtypes = [vp]
-    lib.plbm_closure_set_norm.argtypes = [vp, F, F, F]
+    lib.plbm_closure_set_norm.argtypes = [vp, F, F, F, F]
     lib.plbm_closure_forward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.c_int, vp]
-    lib.plbm_closure_backward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+    lib.plbm_closure_backward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.c_float, vp,
                                           ctypes.POINTER(ctypes.c_double), vp]
     lib.plbm_closure_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
@@ -234,9 +234,11 @@ def _setup_closure(lib):
                                             ctypes.POINTER(ctypes.c_size_t)]
     lib.plbm_restrict.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   vp, vp, vp, vp, vp]
+    lib.plbm_closure_target.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, vp]
 
 
 _setup_closure(lib)
 EXPORTED = EXPORTED + ("plbm_closure_create", "plbm_closure_destroy", "plbm_closure_set_norm",
                        "plbm_closure_forward", "plbm_closure_backward", "plbm_closure_adam",
-                       "plbm_closure_apply", "plbm_closure_activation", "plbm_restrict")
+                       "plbm_closure_apply", "plbm_closure_activation", "plbm_closure_target",
+                       "plbm_restrict")

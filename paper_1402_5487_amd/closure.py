@@ -47,9 +47,12 @@ def split_params(p):
 
 
 class Closure:
-    def __init__(self, nx, ny, frames, device="cuda:0"):
+    """Network workspaces for up to `frames` coarse nx x ny lattices whose
+    populations are stored as `storage` ("f32" or "f64")."""
+
+    def __init__(self, nx, ny, frames, device="cuda:0", storage="f64"):
         self.device = torch.device(device)
-        self.desc = _plbm.desc_default(2, nx, ny, 1.9, "f32")
+        self.desc = _plbm.desc_default(2, nx, ny, 1.9, storage)
         h = ctypes.c_void_p()
         _plbm.check(_plbm.lib.plbm_closure_create(ctypes.byref(self.desc), int(frames),
                                                   ctypes.byref(h)), "plbm_closure_create")
@@ -68,8 +71,11 @@ class Closure:
         except Exception:
             pass
 
-    def set_norm(self, in_mean, in_scale, out_scale):
-        arr = [(ctypes.c_float * 25)(*[float(v) for v in a]) for a in (in_mean, in_scale, out_scale)]
+    def set_norm(self, in_mean, in_scale, out_scale, moment_scale):
+        arr = [(ctypes.c_float * len(a))(*[float(v) for v in a])
+               for a in (in_mean, in_scale, out_scale, moment_scale)]
+        if [len(a) for a in arr] != [25, 25, 25, 4]:
+            raise ValueError("set_norm: 25, 25, 25 and 4 values expected")
         _plbm.check(_plbm.lib.plbm_closure_set_norm(self.handle, *arr), "plbm_closure_set_norm")
 
     def forward(self, params, posts):
@@ -78,10 +84,12 @@ class Closure:
                                                    _ptrs(posts), len(posts), _stream(self.device)),
                     "plbm_closure_forward")
 
-    def backward(self, params, posts, targets, grads, want_loss=True):
+    def backward(self, params, targets, grads, want_loss=True, reg=0.0):
+        """targets: per frame, the increment error d as a float32 (4, ny, nx)
+        device tensor (see target()); reg: minimum-norm weight."""
         loss = ctypes.c_double() if want_loss else None
         _plbm.check(_plbm.lib.plbm_closure_backward(
-            self.handle, ctypes.c_void_p(params.data_ptr()), _ptrs(posts), _ptrs(targets),
+            self.handle, ctypes.c_void_p(params.data_ptr()), _ptrs(targets), float(reg),
             ctypes.c_void_p(grads.data_ptr()), ctypes.byref(loss) if want_loss else None,
             _stream(self.device)), "plbm_closure_backward")
         return loss.value if want_loss else None
@@ -98,19 +106,28 @@ class Closure:
             _stream(self.device)), "plbm_closure_apply")
 
     def activation(self, which):
-        """Copy of an internal activation: bf16 NHWC (which 0..2, 4..6) as
-        float32 (frames, ny, nx, 32), or the FP32 output (which 3)."""
+        """Copy of an internal buffer: bf16 NHWC (which 0..2, 4..6) as float32
+        (frames, ny, nx, 32), the FP32 output (3), the physical correction
+        (7: frames, 25, ny, nx), dL/dm (8: frames, 4, ny, nx) or the last
+        equilibrium shift (9: frames, 25, ny, nx)."""
         ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
         _plbm.check(_plbm.lib.plbm_closure_activation(self.handle, int(which), ctypes.byref(ptr),
                                                       ctypes.byref(nbytes)), "activation")
-        n = self.frames * self.ny * self.nx * CH
-        if which == 3:
-            out = torch.empty(n, dtype=torch.float32, device=self.device)
+        nodes = self.frames * self.ny * self.nx
+        if which == 9:
+            out = torch.empty(nbytes.value // 8, dtype=torch.float64, device=self.device)
+        elif which in (3, 7, 8):
+            out = torch.empty(nbytes.value // 4, dtype=torch.float32, device=self.device)
         else:
-            out = torch.empty(n, dtype=torch.bfloat16, device=self.device)
+            out = torch.empty(nodes * CH, dtype=torch.bfloat16, device=self.device)
         _plbm.check(_plbm.lib.plbm_stream_copy(ptr, ctypes.c_void_p(out.data_ptr()), nbytes.value,
                                                _stream(self.device)), "copy")
-        return out.float().reshape(self.frames, self.ny, self.nx, CH)[:max(self._nf, 1)]
+        nf = max(self._nf, 1)
+        if which in (7, 9):
+            return out.reshape(self.frames, 25, self.ny, self.nx)[:nf]
+        if which == 8:
+            return out.reshape(self.frames, 4, self.ny, self.nx)[:nf]
+        return out.float().reshape(self.frames, self.ny, self.nx, CH)[:nf]
 
 
 def restrict(rho, ux, uy, theta, factor=4):
@@ -123,3 +140,21 @@ def restrict(rho, ux, uy, theta, factor=4):
                                         *[ctypes.c_void_p(t.data_ptr()) for t in out],
                                         _stream(rho.device)), "plbm_restrict")
     return tuple(out)
+
+
+def target(truth_prev, truth_now, model_prev, model_now):
+    """Increment error d (float32 (4, ny, nx) device tensor) of one frame from
+    four (rho, ux, uy, theta) tuples of FP64 device fields
+    (plbm_closure_target)."""
+    fields = [t for group in (truth_prev, truth_now, model_prev, model_now) for t in group]
+    if len(fields) != 16:
+        raise ValueError("target: four (rho, ux, uy, theta) tuples expected")
+    shape = fields[0].shape
+    for t in fields:
+        if t.dtype != torch.float64 or t.shape != shape or not t.is_contiguous():
+            raise ValueError("target: contiguous float64 fields of one shape expected")
+    out = torch.empty((4,) + tuple(shape), dtype=torch.float32, device=fields[0].device)
+    _plbm.check(_plbm.lib.plbm_closure_target(_ptrs(fields), fields[0].numel(),
+                                              ctypes.c_void_p(out.data_ptr()),
+                                              _stream(fields[0].device)), "plbm_closure_target")
+    return out

@@ -1,22 +1,31 @@
 """Training and judging the learned closure with data the method generates.
 
 Host orchestration only: every numerical step is a libplbm call (fine and
-coarse steps, moments, restriction, network forward/backward, Adam, apply).
+coarse steps, moments, restriction, targets, network forward/backward, Adam,
+apply); torch holds the buffers and computes the setup statistics.
 
 Setting (lattice units, acoustic scaling): a fine D2Q25 lattice of
 factor * n nodes per side and a coarse one of n, both with the same velocity
-set, so one coarse step spans `factor` fine steps.  The coarse relaxation
-constant matches the fine viscosity: (1/omega_c - 1/2) = (1/omega_f - 1/2) /
-factor (nu = (1/omega - 1/2) theta dt, Sec. 2.1).
+set and FP64 populations, so one coarse step spans `factor` fine steps.  The
+coarse relaxation constant matches the fine viscosity: (1/omega_c - 1/2) =
+(1/omega_f - 1/2) / factor (nu = (1/omega - 1/2) theta dt, Sec. 2.1).
 
-Frames (teacher forcing): R_t are the restricted fine fields at coarse time t
-(block means of rho, rho u, E).  The coarse post-collision buffer of the
-equilibrium of R_t is the network input; the buffer whose streaming yields
-the equilibrium of R_(t+1) is the target.  The network learns the projected
-difference (it cannot change mass, momentum or energy of a node).
+Frames: R_t are the restricted fine fields at coarse time t (block means of
+rho, rho u, E).  A plain coarse run starts from the equilibrium of R_t0 and
+is restarted from the truth every `restart` steps; after its step n its
+post-collision buffer B_n is a network input, and the target is the error of
+that step's change of the conserved densities,
+    d_n = (cons(R_n) - cons(R_n-1)) - (cons(M_n) - cons(M_n-1)),
+M the coarse run's own moments.  The network learns the correction whose
+streamed moments cancel d_n; it cannot change mass, momentum or energy of a
+node, only move them between nodes.
 
 Judge: on held-out seeds, relative L2 errors of the coarse (rho, u, theta)
-against R_t at matched times, plain coarse step versus corrected step.
+against R_t at matched times, plain coarse run versus corrected run, both
+started once from the equilibrium of R_0.  Each corrected step is the plain
+step, then the network and apply: the correction's moments enter the next
+step as a shift of the equilibrium, so the corrected lattice keeps the plain
+step's non-equilibrium part and the network sees states like its frames.
 """
 import math
 import random
@@ -24,7 +33,7 @@ import random
 import torch
 
 from . import inputs
-from .closure import Closure, init_params, restrict
+from .closure import Closure, init_params, restrict, target
 from .lattice import Lattice
 
 
@@ -34,16 +43,17 @@ def coarse_omega(omega_f, factor):
 
 class Experiment:
     def __init__(self, n_coarse=256, factor=4, theta=0.35, omega_f=1.8, device="cuda:0",
-                 batch=8):
+                 batch=8, restart=25, reg=0.1):
         self.nc, self.factor = n_coarse, factor
         self.nf = n_coarse * factor
         self.theta, self.omega_f = theta, omega_f
         self.omega_c = coarse_omega(omega_f, factor)
         self.device = torch.device(device)
-        self.batch = batch
-        self.net = Closure(self.nc, self.nc, batch, device)
-        self.frames = []          # (post, target) FP32 coarse buffers
+        self.batch, self.restart, self.reg = batch, restart, reg
+        self.net = Closure(self.nc, self.nc, batch, device, storage="f64")
+        self.frames = []          # (post FP64 coarse buffer, d FP32 (4, n, n), steps since restart)
         self.params = None
+        self.bound = 8.0
 
     # -- data ------------------------------------------------------------
     def fine_fields(self, seed):
@@ -52,47 +62,53 @@ class Experiment:
                                        theta=self.theta, uy_amp=s.uy_amp, mode=s.mode,
                                        phase=s.phase)
 
-    def restricted_run(self, seed, times):
-        """Restricted fine fields at the coarse times in `times` (sorted)."""
-        fine = Lattice(2, self.nf, self.nf, omega=self.omega_f, storage="f32",
+    def fine_lattice(self, seed):
+        return Lattice(2, self.nf, self.nf, omega=self.omega_f, storage="f64",
                        device=self.device).init(*self.fine_fields(seed))
-        out, t = {}, 0
-        for want in sorted(set(times)):
-            fine.step((want - t) * self.factor)
-            t = want
-            rho, ux, uy, th = fine.moments()
-            out[want] = restrict(rho, ux, uy, th, self.factor)
-        return out
 
     def coarse_lattice(self):
-        return Lattice(2, self.nc, self.nc, omega=self.omega_c, storage="f32", device=self.device)
+        return Lattice(2, self.nc, self.nc, omega=self.omega_c, storage="f64", device=self.device)
 
-    def make_frame(self, r_t, r_t1):
-        lat = self.coarse_lattice().init(*r_t)
-        lat.step(1)                       # post-collision of the equilibrium of R_t
-        post = lat.f.clone()
-        tgt = self.coarse_lattice().init(*r_t1)
-        return post, tgt.f.clone()
+    def restricted(self, fine):
+        return restrict(*fine.moments(), self.factor)
 
     def generate(self, seeds, per_seed, horizon, rng_seed=0):
+        """per_seed frames from each seed's first `horizon` coarse steps."""
         rng = random.Random(rng_seed)
         for seed in seeds:
-            ts = sorted(rng.sample(range(horizon), per_seed))
-            fields = self.restricted_run(seed, ts + [t + 1 for t in ts])
-            for t in ts:
-                self.frames.append(self.make_frame(fields[t], fields[t + 1]))
+            want = set(rng.sample(range(1, horizon + 1), per_seed))
+            fine = self.fine_lattice(seed)
+            r_prev = self.restricted(fine)
+            coarse, m_prev = None, None
+            for n in range(1, horizon + 1):
+                if (n - 1) % self.restart == 0:
+                    coarse = self.coarse_lattice().init(*r_prev)
+                    m_prev = coarse.moments()
+                fine.step(self.factor)
+                coarse.step(1)
+                r_now = self.restricted(fine)
+                m_now = coarse.moments()
+                if n in want:
+                    k = (n - 1) % self.restart + 1            # steps since the restart
+                    self.frames.append((coarse.f.clone(), target(r_prev, r_now, m_prev, m_now), k))
+                r_prev, m_prev = r_now, m_now
 
     # -- normalisation ---------------------------------------------------
-    def fit_norm(self, sample=16):
-        """Per-population mean/scale of the inputs and scale of the targets
-        (setup statistics over a sample of frames)."""
+    def fit_norm(self, sample=32):
+        """Setup statistics over a sample of frames: per-population mean and
+        scale of the inputs, the rms sigma_j of each target moment, and output
+        scales s_k = 4 sigma w_k (w_k the populations' mean share, sigma the
+        rms over the four moments)."""
         nc = self.nc
-        ps = torch.stack([p.view(nc, 25, nc) for p, _ in self.frames[:sample]])
-        ds = torch.stack([(t - p).view(nc, 25, nc) for p, t in self.frames[:sample]])
+        fr = self.frames[:sample]
+        ps = torch.stack([f[0].view(nc, 25, nc) for f in fr])
+        ds = torch.stack([f[1] for f in fr]).double()
         mean = ps.mean(dim=(0, 1, 3))
         scale = ps.std(dim=(0, 1, 3)).clamp_min(1e-12)
-        oscale = ds.std(dim=(0, 1, 3)).clamp_min(1e-12)
-        self.norm = (mean.tolist(), scale.tolist(), oscale.tolist())
+        msig = ds.pow(2).mean(dim=(0, 2, 3)).sqrt().clamp_min(1e-30)
+        share = mean / mean.sum()
+        oscale = (4.0 * msig.pow(2).mean().sqrt() * share).clamp_min(1e-30)
+        self.norm = (mean.tolist(), scale.tolist(), oscale.tolist(), msig.tolist())
         self.net.set_norm(*self.norm)
 
     # -- training --------------------------------------------------------
@@ -107,47 +123,76 @@ class Experiment:
         hist = []
         for it in range(1, iters + 1):
             idx = [rng.randrange(len(self.frames)) for _ in range(self.batch)]
-            posts = [self.frames[i][0] for i in idx]
-            tgts = [self.frames[i][1] for i in idx]
-            self.net.forward(p, posts)
+            self.net.forward(p, [self.frames[i][0] for i in idx])
             want = log_every and (it % log_every == 0 or it == 1)
-            loss = self.net.backward(p, posts, tgts, g, want_loss=bool(want))
+            loss = self.net.backward(p, [self.frames[i][1] for i in idx], g, want_loss=bool(want),
+                                     reg=self.reg)
             self.net.adam(p, g, m, v, it, lr=lr * min(1.0, it / 50.0))
             if want:
                 hist.append((it, loss))
         torch.cuda.synchronize(self.device)
         return hist
 
-    def loss_on(self, frames):
-        g = torch.zeros_like(self.params)
-        tot = 0.0
+    def loss_on(self, frames, params=None):
+        """Mean moment loss (without the minimum-norm term) over `frames`
+        (whole batches) with `params` (default: the trained ones; zeros give
+        the loss of the plain step)."""
+        params = self.params if params is None else params
+        g = torch.zeros_like(params)
+        tot, nb = 0.0, 0
         for i in range(0, len(frames) - self.batch + 1, self.batch):
-            posts = [f[0] for f in frames[i:i + self.batch]]
-            tgts = [f[1] for f in frames[i:i + self.batch]]
-            self.net.forward(self.params, posts)
-            tot += self.net.backward(self.params, posts, tgts, g, want_loss=True)
-        return tot / max(1, len(frames) // self.batch)
+            self.net.forward(params, [f[0] for f in frames[i:i + self.batch]])
+            tot += self.net.backward(params, [f[1] for f in frames[i:i + self.batch]], g,
+                                     want_loss=True)
+            nb += 1
+        return tot / max(1, nb)
+
+    def explained(self, frames):
+        """(L(no correction), L(trained), 1 - ratio) of the moment loss on
+        `frames`: the share of the plain step's one-step error the corrected
+        step removes."""
+        zero = torch.zeros_like(self.params)
+        l0, l1 = self.loss_on(frames, zero), self.loss_on(frames)
+        return l0, l1, 1.0 - l1 / l0
+
+    def calibrate_bound(self, frames, factor=4.0):
+        """Fallback bound: `factor` times the largest normalised projected
+        correction |Ph y|_k the trained network gives on `frames`, so the
+        fallback engages only on inputs unlike anything seen in training."""
+        s = torch.tensor(self.norm[2], dtype=torch.float32, device=self.device).view(1, 25, 1, 1)
+        g = torch.zeros_like(self.params)
+        worst = 0.0
+        for i in range(0, len(frames) - self.batch + 1, self.batch):
+            chunk = frames[i:i + self.batch]
+            self.net.forward(self.params, [f[0] for f in chunk])
+            self.net.backward(self.params, [f[1] for f in chunk], g, want_loss=False)
+            worst = max(worst, float((self.net.activation(7) / s).abs().max()))
+        self.bound = factor * worst
+        return self.bound
 
     # -- judging ---------------------------------------------------------
-    def judge(self, seed, steps, every, bound=8.0):
+    def judge(self, seed, steps, every, bound=None):
         """Relative L2 errors (rho, |u|, theta) of plain and corrected coarse
         runs against the restricted fine run, averaged over t = every,
         2 every, ..., steps."""
-        times = list(range(0, steps + 1, every))
-        ref = self.restricted_run(seed, times)
-        plain = self.coarse_lattice().init(*ref[0])
-        corr = self.coarse_lattice().init(*ref[0])
+        fine = self.fine_lattice(seed)
+        r0 = self.restricted(fine)
+        plain = self.coarse_lattice().init(*r0)
+        corr = self.coarse_lattice().init(*r0)
+        bound = self.bound if bound is None else bound
         skipped = torch.zeros(1, dtype=torch.int32, device=self.device)
         err = {"plain": [0.0, 0.0, 0.0], "closure": [0.0, 0.0, 0.0]}
-        t = 0
-        for want in times[1:]:
-            plain.step(want - t)
-            for _ in range(want - t):
-                corr.step(1)
-                self.net.forward(self.params, [corr.f])
-                self.net.apply([corr.f], bound=bound, skipped=skipped)
-            t = want
-            r = ref[want]
+        k = 0
+        for n in range(1, steps + 1):
+            fine.step(self.factor)
+            plain.step(1)
+            corr.step(1)
+            self.net.forward(self.params, [corr.f])
+            self.net.apply([corr.f], bound=bound, skipped=skipped)
+            if n % every:
+                continue
+            k += 1
+            r = self.restricted(fine)
             for name, lat in (("plain", plain), ("closure", corr)):
                 m = lat.moments()
                 e = err[name]
@@ -155,11 +200,9 @@ class Experiment:
                 du = torch.sqrt((m[1] - r[1]) ** 2 + (m[2] - r[2]) ** 2).norm()
                 e[1] += float(du / torch.sqrt(r[1] ** 2 + r[2] ** 2).norm())
                 e[2] += float((m[3] - r[3]).norm() / r[3].norm())
-        k = len(times) - 1
         out = {name: [x / k for x in e] for name, e in err.items()}
         out["skipped_nodes"] = int(skipped.item())
-        finite = all(math.isfinite(x) for x in out["closure"])
-        out["finite"] = finite
+        out["finite"] = all(math.isfinite(x) for x in out["closure"])
         return out
 
 
@@ -182,7 +225,7 @@ def forward_rate(ex, reps=20):
     return ms, flops / (ms * 1e-3) / 1e12
 
 
-def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 220),
+def run(n_coarse=256, factor=4, train_seeds=range(100), held_seeds=range(200, 210),
         per_seed=10, horizon=500, iters=2000, batch=8, lr=1e-3, judge_steps=500,
         judge_every=50, log=None):
     """The full learned-closure experiment: generate, train, judge."""
@@ -190,14 +233,24 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
     say = log or (lambda msg: None)
     ex = Experiment(n_coarse=n_coarse, factor=factor, batch=batch)
     t0 = time.perf_counter()
-    ex.generate(train_seeds, per_seed, horizon)
+    ex.generate(held_seeds, 4, horizon, rng_seed=1)
+    held_frames = ex.frames
+    ex.frames = []
+    seeds = list(train_seeds)
+    for i in range(0, len(seeds), 20):
+        ex.generate(seeds[i:i + 20], per_seed, horizon, rng_seed=i)
+        say(f"closure: frames of {min(i + 20, len(seeds))}/{len(seeds)} training seeds")
     gen_s = time.perf_counter() - t0
-    say(f"closure: {len(ex.frames)} frames in {gen_s:.1f} s")
+    say(f"closure: {len(ex.frames)} training and {len(held_frames)} held-out frames in {gen_s:.1f} s")
     ex.fit_norm()
     t0 = time.perf_counter()
     hist = ex.train(iters, lr=lr, log_every=max(1, iters // 10))
     train_s = time.perf_counter() - t0
     say(f"closure: trained {iters} iterations in {train_s:.1f} s, loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g}")
+    l_plain, l_corr, explained = ex.explained(held_frames)
+    say(f"closure: held-out one-step error explained {explained:.3f}")
+    bound = ex.calibrate_bound(ex.frames[:64])
+    say(f"closure: fallback bound {bound:.4g}")
     fwd_ms, fwd_tflops = forward_rate(ex)
     judged = []
     for s in held_seeds:
@@ -207,7 +260,10 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
     return {"coarse": n_coarse, "fine": n_coarse * factor, "omega_c": ex.omega_c,
             "train_seeds": len(list(train_seeds)), "held_out_seeds": len(judged),
             "frames": len(ex.frames), "iters": iters, "batch": batch,
-            "loss_first": hist[0][1], "loss_last": hist[-1][1], "gen_s": gen_s,
+            "restart": ex.restart, "loss_first": hist[0][1], "loss_last": hist[-1][1],
+            "reg": ex.reg, "held_out_frames": len(held_frames),
+            "one_step_loss_plain": l_plain, "one_step_loss_closure": l_corr,
+            "held_out_explained": explained, "fallback_bound": bound, "gen_s": gen_s,
             "train_s": train_s, "ms_per_iter": 1e3 * train_s / iters,
             "forward_ms_per_batch": fwd_ms, "forward_tflops": fwd_tflops,
             "judge_steps": judge_steps,
@@ -216,4 +272,5 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
             "gain": {"rho": plain[0] / corr[0], "u": plain[1] / corr[1],
                      "theta": plain[2] / corr[2]},
             "skipped_nodes": sum(j["skipped_nodes"] for j in judged),
+            "node_steps": len(judged) * judge_steps * n_coarse * n_coarse,
             "finite": all(j["finite"] for j in judged)}

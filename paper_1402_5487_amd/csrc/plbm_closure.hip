@@ -17,10 +17,17 @@
 //    three input rows it needs in LDS channel-major (transposed), and each
 //    wave accumulates 32 x 32 x (64 nodes) MFMA products for its taps; block
 //    partials are summed in a fixed order (deterministic).
-//  * Loss, projection and apply are per-node kernels: the projection removes
+//  * Projection, loss and apply are per-node kernels: the projection removes
 //    the correction's mass, momentum and energy (the invariants of the
 //    collision), orthogonally in the metric of the output scales, so an
-//    applied correction conserves them exactly.
+//    applied correction conserves them exactly.  The loss streams the
+//    correction (pull form) and compares the conserved densities it adds
+//    with a target increment error; its gradient is the adjoint (push) of
+//    the same streaming followed by the projection.  Apply hands those
+//    moments to the next step as a shift of the equilibrium, so the corrected
+//    node keeps the plain step's non-equilibrium part.
+//  * The coarse lattice may hold FP32 or FP64 populations; the network reads
+//    and corrects either.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -52,7 +59,7 @@ typedef uint16_t u16;
 // (no host-to-device copy of pointer tables).
 constexpr int MAX_FRAMES = 64;
 struct PtrList {
-    float *p[MAX_FRAMES];
+    void *p[MAX_FRAMES];
 };
 
 // Normalisation and projection.  With D = diag(s) (output scales) and
@@ -66,6 +73,8 @@ struct ClNorm {
     float out_scale[CREAL];                 // s_k
     float ginv[16];                         // G^-1
     float vx[CREAL], vy[CREAL];
+    int ivx[CREAL], ivy[CREAL];             // the same velocities as node offsets
+    float mw2[4];                           // loss weights 1 / sigma_m^2
 };
 
 __device__ __forceinline__ u16 bf16_bits(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
@@ -96,8 +105,10 @@ __device__ __forceinline__ void project(float (&v)[CREAL], const ClNorm &nm)
 }
 
 // ---------------------------------------------------------------------------
-// population buffer (row layout (y*25 + k)*nx + x, FP32) -> normalised NHWC
+// population buffer (row layout (y*25 + k)*nx + x, FP32 or FP64) -> normalised
+// NHWC bf16; the difference from the mean is taken in the buffer's precision
 // ---------------------------------------------------------------------------
+template <typename T>
 __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, ClNorm nm,
                                                   u16 *__restrict__ x0)
 {
@@ -105,13 +116,14 @@ __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, 
     const int y = blockIdx.y;
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= nx) return;
-    const float *P = post.p[f];
+    const T *P = static_cast<const T *>(post.p[f]);
     uint32_t w[CH / 2];
 #pragma unroll
     for (int c = 0; c < CH; c += 2) {
         float a = 0.f, b = 0.f;
-        if (c < CREAL) a = (P[((size_t)y * CREAL + c) * nx + x] - nm.in_mean[c]) * nm.in_inv[c];
-        if (c + 1 < CREAL) b = (P[((size_t)y * CREAL + c + 1) * nx + x] - nm.in_mean[c + 1]) * nm.in_inv[c + 1];
+        if (c < CREAL) a = (float)(P[((size_t)y * CREAL + c) * nx + x] - (T)nm.in_mean[c]) * nm.in_inv[c];
+        if (c + 1 < CREAL)
+            b = (float)(P[((size_t)y * CREAL + c + 1) * nx + x] - (T)nm.in_mean[c + 1]) * nm.in_inv[c + 1];
         w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
     }
     uint4 *dst = reinterpret_cast<uint4 *>(x0 + (((size_t)f * ny + y) * nx + x) * CH);
@@ -280,39 +292,39 @@ __global__ __launch_bounds__(256) void k_cl_wgrad_reduce(const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Loss, in normalised coordinates: r = Ph (y - (P_target - P) / s),
-// L = mean over nodes of |r|^2, dL/dy = (2 / N) r (Ph symmetric idempotent)
-// -> bf16 NHWC (zero in the padding).
+// Moment-form loss.  Physical correction c = s * Ph y (planes [f][k][y][x]);
+// the corrected buffer streamed in the pull form adds to node x the conserved
+// densities m(x) = sum_k Phi_k (c_k(x - v_k) - c_k(x)) (flux form: the second
+// term is zero for a moment-free c, and with it the domain totals of m vanish
+// exactly although c is stored in FP32); with the target increment error
+// d (planes [j][y][x] per frame) the residual is r = m - d and
+//   L = (1/N) sum_x [sum_j w_j r_j^2 + beta |Ph y|^2],   w_j = 1 / sigma_j^2.
+// The moments fix only 4 of a node's 21 free correction components; the
+// minimum-norm term picks the smallest correction that explains them.
+// dL/dc_k(x) = sum_j Phi_jk (a_j(x + v_k) - a_j(x)) with a = (2/N) w r (the
+// push); the a_j(x) part lies in the span Ph removes, so
+// dL/dy = Ph (s * push + (2 beta / N) y) since Ph is symmetric idempotent.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cl_loss(const float *__restrict__ y3, PtrList post,
-                                                 PtrList target, int nx, int ny, ClNorm nm, float inv_n,
-                                                 u16 *__restrict__ dy3, float *__restrict__ lpart)
+__global__ __launch_bounds__(256) void k_cl_corr(const float *__restrict__ y3, int nx, int ny, ClNorm nm,
+                                                 float reg, float *__restrict__ C, float *__restrict__ lpart)
 {
     __shared__ float red[4];
     const int f = blockIdx.z, y = blockIdx.y;
     const int x = blockIdx.x * 256 + threadIdx.x;
     float lsum = 0.f;
     if (x < nx) {
+        const size_t plane = (size_t)nx * ny;
         const size_t node = ((size_t)f * ny + y) * nx + x;
-        float r[CREAL];
+        float d[CREAL];
+#pragma unroll
+        for (int k = 0; k < CREAL; ++k) d[k] = y3[node * CH + k];
+        project(d, nm);
 #pragma unroll
         for (int k = 0; k < CREAL; ++k) {
-            const size_t e = ((size_t)y * CREAL + k) * nx + x;
-            r[k] = y3[node * CH + k] - (target.p[f][e] - post.p[f][e]) / nm.out_scale[k];
+            lsum += d[k] * d[k];
+            C[((size_t)f * CREAL + k) * plane + (size_t)y * nx + x] = nm.out_scale[k] * d[k];
         }
-        project(r, nm);
-#pragma unroll
-        for (int k = 0; k < CREAL; ++k) lsum += r[k] * r[k];
-        uint32_t w[CH / 2];
-#pragma unroll
-        for (int c = 0; c < CH; c += 2) {
-            const float a = c < CREAL ? 2.f * inv_n * r[c] : 0.f;
-            const float b = c + 1 < CREAL ? 2.f * inv_n * r[c + 1] : 0.f;
-            w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
-        }
-        uint4 *dst = reinterpret_cast<uint4 *>(dy3 + node * CH);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dst[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+        lsum *= reg;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
@@ -323,18 +335,136 @@ __global__ __launch_bounds__(256) void k_cl_loss(const float *__restrict__ y3, P
             (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// ---------------------------------------------------------------------------
-// Apply: P += s * Ph y where the correction is finite and every normalised
-// component |Ph y|_k is within bound; otherwise the node keeps the plain
-// post-collision populations (fallback) and the skip counter is incremented.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cl_apply(const float *__restrict__ y3, PtrList post, int nx,
-                                                  int ny, ClNorm nm, float bound,
-                                                  unsigned *__restrict__ skipped)
+__global__ __launch_bounds__(256) void k_cl_mloss(const float *__restrict__ C, PtrList target, int nx, int ny,
+                                                  ClNorm nm, float inv_n, float *__restrict__ A,
+                                                  float *__restrict__ lpart)
+{
+    __shared__ float red[4];
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    float lsum = 0.f;
+    if (x < nx) {
+        const size_t plane = (size_t)nx * ny;
+        float m[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < CREAL; ++k) {
+            int xs = x - nm.ivx[k], ys = y - nm.ivy[k];
+            xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+            ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+            const float *ck = C + ((size_t)f * CREAL + k) * plane;
+            const float c = ck[(size_t)ys * nx + xs] - ck[(size_t)y * nx + x];
+            const float vx = nm.vx[k], vy = nm.vy[k];
+            m[0] += c;
+            m[1] += vx * c;
+            m[2] += vy * c;
+            m[3] += (vx * vx + vy * vy) * c;
+        }
+        const float *d = static_cast<const float *>(target.p[f]);
+        const size_t at = (size_t)y * nx + x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float r = m[j] - d[j * plane + at];
+            lsum += nm.mw2[j] * r * r;
+            A[((size_t)f * 4 + j) * plane + at] = 2.f * inv_n * nm.mw2[j] * r;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        lpart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] +=
+            (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_cl_mgrad(const float *__restrict__ A, const float *__restrict__ y3,
+                                                  int nx, int ny, ClNorm nm, float reg2n,
+                                                  u16 *__restrict__ dy3)
 {
     const int f = blockIdx.z, y = blockIdx.y;
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= nx) return;
+    const size_t plane = (size_t)nx * ny;
+    const size_t node = ((size_t)f * ny + y) * nx + x;
+    float t[CREAL];
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        int xs = x + nm.ivx[k], ys = y + nm.ivy[k];
+        xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+        const size_t at = (size_t)ys * nx + xs;
+        const float *a = A + (size_t)f * 4 * plane + at;
+        const float vx = nm.vx[k], vy = nm.vy[k];
+        t[k] = nm.out_scale[k] * (a[0] + vx * a[plane] + vy * a[2 * plane] + (vx * vx + vy * vy) * a[3 * plane]) +
+               reg2n * y3[node * CH + k];
+    }
+    project(t, nm);
+    uint32_t w[CH / 2];
+#pragma unroll
+    for (int c = 0; c < CH; c += 2) {
+        const float a = c < CREAL ? t[c] : 0.f;
+        const float b = c + 1 < CREAL ? t[c + 1] : 0.f;
+        w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(dy3 + (((size_t)f * ny + y) * nx + x) * CH);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dst[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+}
+
+// Increment error d = (cons(truth_now) - cons(truth_prev)) - (cons(model_now)
+// - cons(model_prev)), cons(rho, u, theta) = (rho, rho u, rho (2 theta + |u|^2)),
+// in FP64, rounded once to FP32 planes [j][node].
+struct Fields16 {
+    const double *p[16];
+};
+
+__device__ __forceinline__ void cons4(const Fields16 &F, int b, size_t i, double (&c)[4])
+{
+    const double r = F.p[b][i], u = F.p[b + 1][i], w = F.p[b + 2][i], t = F.p[b + 3][i];
+    c[0] = r;
+    c[1] = r * u;
+    c[2] = r * w;
+    c[3] = r * (2.0 * t + u * u + w * w);
+}
+
+__global__ __launch_bounds__(256) void k_cl_target(Fields16 F, size_t n, float *__restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double tp[4], tn[4], mp[4], mn[4];
+    cons4(F, 0, i, tp);
+    cons4(F, 4, i, tn);
+    cons4(F, 8, i, mp);
+    cons4(F, 12, i, mn);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j * n + i] = (float)((tn[j] - tp[j]) - (mn[j] - mp[j]));
+}
+
+// ---------------------------------------------------------------------------
+// Apply, as an equilibrium shift.  The correction's streamed moments
+// g(x) = sum_k Phi_k (c_k(x - v_k) - c_k(x)) are the change of node x's conserved
+// densities; they are given to the populations f = pull(P) of the next step
+// as  f <- f + f_eq(m + g) - f_eq(m)  (m the node's own moments), so the
+// node's moments become m + g exactly and its non-equilibrium part f - f_eq
+// is the plain step's.  In the pull layout the shift of population k at
+// node x is stored at x - v_k.
+//
+// 1. k_cl_corr_apply: c = s * Ph y where every normalised component is
+//    finite and within bound, else c = 0 (fallback, counted in *skipped);
+// 2. k_cl_shift: per node, m from the pulled populations (FP64), g from c,
+//    delta = f_eq(m + g) - f_eq(m) (zero if the shifted density or
+//    temperature would not be positive);
+// 3. k_cl_scatter: P_k(x) += delta_k(x + v_k) in the storage type (delta is
+//    kept in FP64, so FP64 lattices conserve the totals to FP64 rounding).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cl_corr_apply(const float *__restrict__ y3, int nx, int ny, ClNorm nm,
+                                                       float bound, float *__restrict__ C,
+                                                       unsigned *__restrict__ skipped)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const size_t plane = (size_t)nx * ny;
     const size_t node = ((size_t)f * ny + y) * nx + x;
     float d[CREAL];
 #pragma unroll
@@ -343,13 +473,77 @@ __global__ __launch_bounds__(256) void k_cl_apply(const float *__restrict__ y3, 
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < CREAL; ++k) ok = ok && (fabsf(d[k]) <= bound);
-    if (!ok) {
-        if (skipped) atomicAdd(skipped, 1u);
-        return;
-    }
-    float *P = post.p[f];
+    if (!ok && skipped) atomicAdd(skipped, 1u);
 #pragma unroll
-    for (int k = 0; k < CREAL; ++k) P[((size_t)y * CREAL + k) * nx + x] += nm.out_scale[k] * d[k];
+    for (int k = 0; k < CREAL; ++k)
+        C[((size_t)f * CREAL + k) * plane + (size_t)y * nx + x] = ok ? nm.out_scale[k] * d[k] : 0.f;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__restrict__ C, int nx, int ny,
+                                                  ClNorm nm, KParams kp, double *__restrict__ delta)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const size_t plane = (size_t)nx * ny;
+    const T *P = static_cast<const T *>(post.p[f]);
+    double fp[NQ];
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        int xs = x - nm.ivx[k], ys = y - nm.ivy[k];
+        xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+        fp[k] = (double)P[((size_t)ys * CREAL + k) * nx + xs];
+        const float *ck = C + ((size_t)f * CREAL + k) * plane;
+        const double c = (double)ck[(size_t)ys * nx + xs] - (double)ck[(size_t)y * nx + x];
+        const double vx = nm.vx[k], vy = nm.vy[k];
+        g[0] += c;
+        g[1] += vx * c;
+        g[2] += vy * c;
+        g[3] += (vx * vx + vy * vy) * c;
+    }
+    double rho, jx, jy, e;
+    sums2d<Fp64Math>(fp, kp, rho, jx, jy, e);
+    const double r1 = rho + g[0];
+    const double ux0 = jx / rho, uy0 = jy / rho;
+    const double th0 = 0.5 * (e / rho - ux0 * ux0 - uy0 * uy0);
+    const double ux1 = (jx + g[1]) / r1, uy1 = (jy + g[2]) / r1;
+    const double th1 = 0.5 * ((e + g[3]) / r1 - ux1 * ux1 - uy1 * uy1);
+    const bool ok = r1 > 0.0 && th1 > 0.0 && isfinite(th1) && isfinite(ux1) && isfinite(uy1);
+    double a0[Q], b0[Q], a1[Q], b1[Q];
+    rule1d<Fp64Math>(ux0, th0, kp, a0);
+    rule1d<Fp64Math>(uy0, th0, kp, b0);
+    rule1d<Fp64Math>(ux1, th1, kp, a1);
+    rule1d<Fp64Math>(uy1, th1, kp, b1);
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            // products rounded on their own (no fused multiply-subtract), so
+            // a zero moment change gives a zero shift bit for bit
+            const double dlt = __dmul_rn(__dmul_rn(r1, a1[i]), b1[j]) - __dmul_rn(__dmul_rn(rho, a0[i]), b0[j]);
+            delta[((size_t)f * CREAL + i + Q * j) * plane + (size_t)y * nx + x] = ok ? dlt : 0.0;
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_scatter(PtrList post, const double *__restrict__ delta, int nx,
+                                                    int ny, ClNorm nm)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const size_t plane = (size_t)nx * ny;
+    T *P = static_cast<T *>(post.p[f]);
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        int xs = x + nm.ivx[k], ys = y + nm.ivy[k];
+        xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+        P[((size_t)y * CREAL + k) * nx + x] += (T)delta[((size_t)f * CREAL + k) * plane + (size_t)ys * nx + xs];
+    }
 }
 
 // FP32 parameters -> bf16 [t][o][i] (forward) and [t][i][o] (input gradient)
@@ -416,6 +610,7 @@ int ck(hipError_t e) { return e == hipSuccess ? PLBM_OK : PLBM_EHIP; }
 
 struct plbm_closure {
     int nx = 0, ny = 0, frames = 0;
+    bool f64 = false;                          // coarse populations FP64 (else FP32)
     ClNorm nm;
     u16 *wf = nullptr, *wt = nullptr;          // bf16 weights
     u16 *x0 = nullptr, *a1 = nullptr, *a2 = nullptr;
@@ -423,6 +618,10 @@ struct plbm_closure {
     u16 *dy3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
     float *part = nullptr;                     // weight-gradient partials
     float *lpart = nullptr;                    // loss partials
+    float *corr = nullptr;                     // c = s * Ph y, planes [f][k][y][x]
+    float *mres = nullptr;                     // (2/N) w r, planes [f][j][y][x]
+    double *shift = nullptr;                   // equilibrium shift, planes [f][k][y][x]
+    KParams kp;                                // the coarse lattice's rule
     int nwblk = 0, nlblk = 0;
     int frames_in_fwd = 0;
     const float *cast_from = nullptr;
@@ -461,12 +660,13 @@ int set_projection(ClNorm &nm)
     return PLBM_OK;
 }
 
-int make_list(PtrList &l, const float *const *host, int n)
+template <typename P>
+int make_list(PtrList &l, const P *host, int n)
 {
     std::memset(&l, 0, sizeof(l));
     for (int i = 0; i < n; ++i) {
         if (!host[i]) return PLBM_EINVAL;
-        l.p[i] = const_cast<float *>(host[i]);
+        l.p[i] = const_cast<void *>(static_cast<const void *>(host[i]));
     }
     return PLBM_OK;
 }
@@ -483,7 +683,8 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
 {
     if (!coarse || !out || frames < 1 || frames > MAX_FRAMES) return PLBM_EINVAL;
     *out = nullptr;
-    if (coarse->dim != 2 || coarse->storage != PLBM_F32) return PLBM_EUNSUPPORTED;
+    if (coarse->dim != 2 || (coarse->storage != PLBM_F32 && coarse->storage != PLBM_F64))
+        return PLBM_EUNSUPPORTED;
     const int rc0 = plbm::validate(coarse);
     if (rc0 != PLBM_OK) return rc0;
     if (coarse->nx % WG_SEG != 0 || coarse->nx < WG_SEG) return PLBM_EUNSUPPORTED;
@@ -494,13 +695,25 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
     c->nx = coarse->nx;
     c->ny = coarse->ny;
     c->frames = frames;
+    c->f64 = coarse->storage == PLBM_F64;
+    c->kp = kp;
     std::memset(&c->nm, 0, sizeof(c->nm));
     for (int k = 0; k < CREAL; ++k) {
-        c->nm.vx[k] = (float)coarse->v[k % 5];
-        c->nm.vy[k] = (float)coarse->v[k / 5];
+        const double vx = coarse->v[k % 5], vy = coarse->v[k / 5];
+        // streaming offsets of the loss: whole nodes, one periodic wrap at most
+        if (vx != std::rint(vx) || vy != std::rint(vy) || std::fabs(vx) >= coarse->nx ||
+            std::fabs(vy) >= coarse->ny) {
+            delete c;
+            return PLBM_EUNSUPPORTED;
+        }
+        c->nm.vx[k] = (float)vx;
+        c->nm.vy[k] = (float)vy;
+        c->nm.ivx[k] = (int)vx;
+        c->nm.ivy[k] = (int)vy;
         c->nm.in_inv[k] = 1.f;
         c->nm.out_scale[k] = 1.f;
     }
+    for (int j = 0; j < 4; ++j) c->nm.mw2[j] = 1.f;
     if (set_projection(c->nm) != PLBM_OK) {
         delete c;
         return PLBM_ESINGULAR;
@@ -519,7 +732,10 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
               hipMalloc((void **)&c->dz2, nodes * CH * sizeof(u16)) == hipSuccess &&
               hipMalloc((void **)&c->dz1, nodes * CH * sizeof(u16)) == hipSuccess &&
               hipMalloc((void **)&c->part, (size_t)c->nwblk * (LAYER_W + CH) * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&c->lpart, (size_t)c->nlblk * sizeof(float)) == hipSuccess;
+              hipMalloc((void **)&c->lpart, (size_t)c->nlblk * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->corr, nodes * CREAL * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->mres, nodes * 4 * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->shift, nodes * CREAL * sizeof(double)) == hipSuccess;
     if (!ok) {
         plbm_closure_destroy(c);
         return PLBM_EHIP;
@@ -533,7 +749,7 @@ extern "C" int plbm_closure_destroy(plbm_closure *c)
     if (!c) return PLBM_EINVAL;
     (void)hipDeviceSynchronize();
     void *ptrs[] = {c->wf, c->wt, c->x0, c->a1, c->a2, c->y3, c->dy3, c->dz2, c->dz1, c->part,
-                    c->lpart};
+                    c->lpart, c->corr, c->mres, c->shift};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -541,10 +757,16 @@ extern "C" int plbm_closure_destroy(plbm_closure *c)
 }
 
 extern "C" int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, const float *in_scale,
-                                     const float *out_scale)
+                                     const float *out_scale, const float *moment_scale)
 {
-    if (!c || !in_mean || !in_scale || !out_scale) return PLBM_EINVAL;
+    if (!c || !in_mean || !in_scale || !out_scale || !moment_scale) return PLBM_EINVAL;
     ClNorm nm = c->nm;
+    for (int j = 0; j < 4; ++j) {
+        if (!(moment_scale[j] > 0.f) || !std::isfinite(moment_scale[j])) return PLBM_EINVAL;
+        const double w = 1.0 / ((double)moment_scale[j] * moment_scale[j]);
+        if (!std::isfinite((float)w)) return PLBM_EINVAL;
+        nm.mw2[j] = (float)w;
+    }
     for (int k = 0; k < CREAL; ++k) {
         if (!(in_scale[k] > 0.f) || !(out_scale[k] > 0.f) || !std::isfinite(in_mean[k]) ||
             !std::isfinite(in_scale[k]) || !std::isfinite(out_scale[k]))
@@ -559,7 +781,7 @@ extern "C" int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, cons
     return PLBM_OK;
 }
 
-extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const float *const *post,
+extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const void *const *post,
                                     int frames, void *stream)
 {
     if (!c || !params || !post || frames < 1 || frames > c->frames) return PLBM_EINVAL;
@@ -572,7 +794,10 @@ extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const 
     if (rc != PLBM_OK) return rc;
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
     const dim3 gc((c->nx / 32 + 3) / 4, c->ny, frames);
-    hipLaunchKernelGGL(k_cl_input, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, c->x0);
+    if (c->f64)
+        hipLaunchKernelGGL(k_cl_input<double>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, c->x0);
+    else
+        hipLaunchKernelGGL(k_cl_input<float>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, c->x0);
     // bias of layer l: params + l * LAYER_P + LAYER_W
     hipLaunchKernelGGL(k_cl_conv<0>, gc, dim3(256), 0, st, c->x0, c->wf, params + LAYER_W, nullptr, c->a1,
                        c->nx, c->ny);
@@ -584,16 +809,15 @@ extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const 
     return ck(hipGetLastError());
 }
 
-extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const float *const *post,
-                                     const float *const *target, float *grads, double *loss,
-                                     void *stream)
+extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const float *const *target,
+                                     float reg, float *grads, double *loss, void *stream)
 {
-    if (!c || !params || !post || !target || !grads || c->frames_in_fwd < 1) return PLBM_EINVAL;
+    if (!c || !params || !target || !grads || c->frames_in_fwd < 1 || !(reg >= 0.f) || !std::isfinite(reg))
+        return PLBM_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int frames = c->frames_in_fwd;
-    PtrList pl, tl;
-    int rc = make_list(pl, post, frames);
-    if (rc == PLBM_OK) rc = make_list(tl, target, frames);
+    PtrList tl;
+    int rc = make_list(tl, target, frames);
     if (rc != PLBM_OK) return rc;
     (void)hipGetLastError();
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
@@ -601,8 +825,11 @@ extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const
     const dim3 gw((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS), 1, frames);
     const int nwblk = (int)(gw.x * gw.z);
     const float inv_n = 1.0f / ((float)frames * c->nx * c->ny);
-    hipLaunchKernelGGL(k_cl_loss, gn, dim3(256), 0, st, c->y3, pl, tl, c->nx, c->ny, c->nm, inv_n, c->dy3,
+    hipLaunchKernelGGL(k_cl_corr, gn, dim3(256), 0, st, c->y3, c->nx, c->ny, c->nm, reg, c->corr, c->lpart);
+    hipLaunchKernelGGL(k_cl_mloss, gn, dim3(256), 0, st, c->corr, tl, c->nx, c->ny, c->nm, inv_n, c->mres,
                        c->lpart);
+    hipLaunchKernelGGL(k_cl_mgrad, gn, dim3(256), 0, st, c->mres, c->y3, c->nx, c->ny, c->nm, 2.f * reg * inv_n,
+                       c->dy3);
     // layer 3: dW3 from a2 and dy3; dz2 = (W3^T dy3) * (a2 > 0)
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a2, c->dy3, c->nx, c->ny, c->part);
     hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
@@ -645,7 +872,7 @@ extern "C" int plbm_closure_adam(plbm_closure *c, float *params, const float *gr
     return ck(hipGetLastError());
 }
 
-extern "C" int plbm_closure_apply(plbm_closure *c, float *const *post, int frames, float bound,
+extern "C" int plbm_closure_apply(plbm_closure *c, void *const *post, int frames, float bound,
                                   unsigned *skipped, void *stream)
 {
     if (!c || !post || frames < 1 || frames != c->frames_in_fwd || !(bound > 0.f)) return PLBM_EINVAL;
@@ -655,7 +882,16 @@ extern "C" int plbm_closure_apply(plbm_closure *c, float *const *post, int frame
     if (rc != PLBM_OK) return rc;
     (void)hipGetLastError();
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
-    hipLaunchKernelGGL(k_cl_apply, gn, dim3(256), 0, st, c->y3, pl, c->nx, c->ny, c->nm, bound, skipped);
+    hipLaunchKernelGGL(k_cl_corr_apply, gn, dim3(256), 0, st, c->y3, c->nx, c->ny, c->nm, bound, c->corr, skipped);
+    if (c->f64) {
+        hipLaunchKernelGGL(k_cl_shift<double>, gn, dim3(256), 0, st, pl, c->corr, c->nx, c->ny, c->nm, c->kp,
+                           c->shift);
+        hipLaunchKernelGGL(k_cl_scatter<double>, gn, dim3(256), 0, st, pl, c->shift, c->nx, c->ny, c->nm);
+    } else {
+        hipLaunchKernelGGL(k_cl_shift<float>, gn, dim3(256), 0, st, pl, c->corr, c->nx, c->ny, c->nm, c->kp,
+                           c->shift);
+        hipLaunchKernelGGL(k_cl_scatter<float>, gn, dim3(256), 0, st, pl, c->shift, c->nx, c->ny, c->nm);
+    }
     return ck(hipGetLastError());
 }
 
@@ -673,6 +909,9 @@ extern "C" int plbm_closure_activation(const plbm_closure *c, int which, const v
     case 4: p = c->dy3; break;
     case 5: p = c->dz2; break;
     case 6: p = c->dz1; break;
+    case 7: p = c->corr; b = nodes * CREAL * sizeof(float); break;
+    case 8: p = c->mres; b = nodes * 4 * sizeof(float); break;
+    case 9: p = c->shift; b = nodes * CREAL * sizeof(double); break;
     default: return PLBM_EINVAL;
     }
     *ptr = p;
@@ -691,5 +930,19 @@ extern "C" int plbm_restrict(const double *rho, const double *ux, const double *
     const int cnx = fnx / factor, cny = fny / factor;
     hipLaunchKernelGGL(k_restrict, dim3((cnx + 255) / 256, cny), dim3(256), 0, st, rho, ux, uy, theta, fnx,
                        fny, factor, crho, cux, cuy, ctheta);
+    return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_target(const double *const *fields, size_t nodes, float *out, void *stream)
+{
+    if (!fields || !out || nodes == 0) return PLBM_EINVAL;
+    Fields16 F;
+    for (int i = 0; i < 16; ++i) {
+        if (!fields[i]) return PLBM_EINVAL;
+        F.p[i] = fields[i];
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_cl_target, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, st, F, nodes, out);
     return ck(hipGetLastError());
 }
