@@ -18,7 +18,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import V5, pulled_state, rel_err
+from helpers import rest_weights, V5, pulled_state, rel_err
 from paper_1402_5487_amd import _plbm, inputs
 from paper_1402_5487_amd.lattice import Lattice
 
@@ -129,6 +129,27 @@ def test_step_dev_storage_parity(storage, half_ulp):
     assert errs[1] < 3 * bound and errs[2] < 3 * bound, (errs, bound)
 
 
+@pytest.mark.parametrize("storage,half_ulp", [("f16dev", 2.0 ** -2), ("bf16dev", 2.0)])
+@pytest.mark.parametrize("nx", [512, 300])     # whole 256-node tiles, and a ragged last tile
+def test_dev_storage_step_matches_oracle_step(storage, half_ulp, nx):
+    """One step from the GPU's own 16-bit state, population by population:
+    the oracle's FP64 step of the decoded state, within the rounding of the
+    stored deviation (half an ulp of |h| < 2^10, doubled for growth) plus
+    FP32 arithmetic."""
+    ny, th = 24, 0.35
+    fields = inputs.kelvin_helmholtz(nx, ny, u0=0.1, delta=3.0, theta=th)
+    lat = Lattice(2, nx, ny, omega=1.8, storage=storage, theta0=th).init(*fields)
+    lat.step(3)
+    pre = pulled_state(lat.f, lat)
+    lat.step(1)
+    got = pulled_state(lat.f, lat)
+    ref = oracle.Lattice(2, nx, ny, omega=1.8).step(pre, 1)
+    scale = np.array([lat.desc.scale[k] for k in range(25)])
+    # population k of the pulled state was stored with the scale of k
+    bound = 2 * half_ulp * scale[:, None, None] + 64 * EPS32 * np.abs(ref)
+    assert np.all(np.abs(got - ref) <= bound), float((np.abs(got - ref) / bound).max())
+
+
 # --------------------------------------------------------------------------
 # 1D D1Q5 shock tube with zero-gradient ghost ends
 # --------------------------------------------------------------------------
@@ -218,11 +239,12 @@ def test_checkpoint_resume_is_bitwise():
 # populations equal the oracle's collision of the same pulled state
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
 def test_full_size_sampled_nodes(storage):
     n = 4096
     fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80, theta=0.35)
-    lat = Lattice(2, n, n, omega=1.8, storage=storage).init(*fields)
+    lat = Lattice(2, n, n, omega=1.8, storage=storage, theta0=0.35 if storage == "f16dev" else None)
+    lat.init(*fields)
     lat.step(3)
     before = lat.f.clone()
     lat.step(1)
@@ -236,10 +258,23 @@ def test_full_size_sampled_nodes(storage):
     dst = after.view(n, 25, n).transpose(0, 1)
     one = oracle.Lattice(2, 1, 1, omega=1.8)
     tol = 1e-14 if storage == "f64" else 64 * EPS32
+    if storage == "f16dev":
+        w = rest_weights(lat.desc.theta0)
+        base = np.array([lat.desc.rho0 * w[k % 5] * w[k // 5] for k in range(25)],
+                        dtype=np.float32).astype(np.float64)
+        scale = np.array([lat.desc.scale[k] for k in range(25)])
+        dec = lambda h, k: base[k] + scale[k] * float(h)
+    else:
+        dec = lambda h, k: float(h)
     for y, x in zip(ys, xs):
-        pre = np.array([src[k, (y - V5[k // 5]) % n, (x - V5[k % 5]) % n].item()
+        pre = np.array([dec(src[k, (y - V5[k // 5]) % n, (x - V5[k % 5]) % n].double().item(), k)
                         for k in range(25)]).reshape(25, 1, 1)
         post = one.step(pre, 1).ravel()       # 1x1 periodic lattice: pure collision
-        got = np.array([dst[k, y, x].item() for k in range(25)])
-        assert np.abs(got - post).max() < tol * np.abs(post).max(), (y, x)
+        got = np.array([dec(dst[k, y, x].double().item(), k) for k in range(25)])
+        if storage == "f16dev":
+            # half an ulp of the stored deviation (|h| < 2^10), doubled, plus FP32
+            bound = 2 * 2.0 ** -2 * scale + 64 * EPS32 * np.abs(post)
+            assert np.all(np.abs(got - post) <= bound), (y, x)
+        else:
+            assert np.abs(got - post).max() < tol * np.abs(post).max(), (y, x)
     assert plane == n * n
