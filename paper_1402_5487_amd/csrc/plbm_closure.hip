@@ -275,19 +275,36 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
     if (wv == 0 && l < CH) part[nblk * LAYER_W + blk * CH + l] = bsum;
 }
 
-// Sum the block partials in a fixed order into the flat gradient of one layer.
-__global__ __launch_bounds__(256) void k_cl_wgrad_reduce(const float *__restrict__ part, int nblk,
+// Sum the block partials in a fixed order into the flat gradient of one
+// layer, in two passes: slice z of the first pass sums blocks z, z + WR_SLICES,
+// ... ; the second sums the slices in order.  Deterministic, and wide enough
+// to keep the memory system busy (the partials of 16 row bands x 8 frames are
+// several MB).
+constexpr int WR_SLICES = 32;
+
+__device__ __forceinline__ float part_at(const float *part, int nblk, int b, int i)
+{
+    return i < LAYER_W ? part[(size_t)b * LAYER_W + i] : part[(size_t)nblk * LAYER_W + (size_t)b * CH + (i - LAYER_W)];
+}
+
+__global__ __launch_bounds__(256) void k_cl_wgrad_slices(const float *__restrict__ part, int nblk,
+                                                         float *__restrict__ slices)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x, z = blockIdx.y;
+    if (i >= LAYER_P) return;
+    float s = 0.f;
+    for (int b = z; b < nblk; b += WR_SLICES) s += part_at(part, nblk, b, i);
+    slices[(size_t)z * LAYER_P + i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_cl_wgrad_reduce(const float *__restrict__ slices,
                                                          float *__restrict__ grad)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= LAYER_P) return;
     float s = 0.f;
-    if (i < LAYER_W) {
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * LAYER_W + i];
-    } else {
-        const int o = i - LAYER_W;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)nblk * LAYER_W + (size_t)b * CH + o];
-    }
+#pragma unroll 8
+    for (int z = 0; z < WR_SLICES; ++z) s += slices[(size_t)z * LAYER_P + i];
     grad[i] = s;
 }
 
@@ -483,6 +500,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__restrict__ C, int nx, int ny,
                                                   ClNorm nm, KParams kp, double *__restrict__ delta)
 {
+    // no fused multiply-adds: the two equilibria below are evaluated by the
+    // same rounded operations, so a zero moment change gives a zero shift
+#pragma clang fp contract(off)
     const int f = blockIdx.z, y = blockIdx.y;
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= nx) return;
@@ -521,9 +541,7 @@ __global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__r
     for (int j = 0; j < Q; ++j)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            // products rounded on their own (no fused multiply-subtract), so
-            // a zero moment change gives a zero shift bit for bit
-            const double dlt = __dmul_rn(__dmul_rn(r1, a1[i]), b1[j]) - __dmul_rn(__dmul_rn(rho, a0[i]), b0[j]);
+            const double dlt = r1 * a1[i] * b1[j] - rho * a0[i] * b0[j];
             delta[((size_t)f * CREAL + i + Q * j) * plane + (size_t)y * nx + x] = ok ? dlt : 0.0;
         }
 }
@@ -617,6 +635,7 @@ struct plbm_closure {
     float *y3 = nullptr;
     u16 *dy3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
     float *part = nullptr;                     // weight-gradient partials
+    float *slices = nullptr;                   // their first-pass sums
     float *lpart = nullptr;                    // loss partials
     float *corr = nullptr;                     // c = s * Ph y, planes [f][k][y][x]
     float *mres = nullptr;                     // (2/N) w r, planes [f][j][y][x]
@@ -669,6 +688,13 @@ int make_list(PtrList &l, const P *host, int n)
         l.p[i] = const_cast<void *>(static_cast<const void *>(host[i]));
     }
     return PLBM_OK;
+}
+
+void reduce_wgrad(plbm_closure *c, int nwblk, float *grad, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cl_wgrad_slices, dim3((LAYER_P + 255) / 256, WR_SLICES), dim3(256), 0, st, c->part,
+                       nwblk, c->slices);
+    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->slices, grad);
 }
 
 int cast_weights(plbm_closure *c, const float *params, hipStream_t st)
@@ -733,6 +759,7 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
               hipMalloc((void **)&c->dz1, nodes * CH * sizeof(u16)) == hipSuccess &&
               hipMalloc((void **)&c->part, (size_t)c->nwblk * (LAYER_W + CH) * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->lpart, (size_t)c->nlblk * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->slices, (size_t)WR_SLICES * LAYER_P * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->corr, nodes * CREAL * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->mres, nodes * 4 * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->shift, nodes * CREAL * sizeof(double)) == hipSuccess;
@@ -749,7 +776,7 @@ extern "C" int plbm_closure_destroy(plbm_closure *c)
     if (!c) return PLBM_EINVAL;
     (void)hipDeviceSynchronize();
     void *ptrs[] = {c->wf, c->wt, c->x0, c->a1, c->a2, c->y3, c->dy3, c->dz2, c->dz1, c->part,
-                    c->lpart, c->corr, c->mres, c->shift};
+                    c->lpart, c->corr, c->mres, c->shift, c->slices};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -832,20 +859,17 @@ extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const
                        c->dy3);
     // layer 3: dW3 from a2 and dy3; dz2 = (W3^T dy3) * (a2 > 0)
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a2, c->dy3, c->nx, c->ny, c->part);
-    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
-                       grads + 2 * LAYER_P);
+    reduce_wgrad(c, nwblk, grads + 2 * LAYER_P, st);
     hipLaunchKernelGGL(k_cl_conv<2>, gc, dim3(256), 0, st, c->dy3, c->wt + 2 * LAYER_W, nullptr, c->a2,
                        c->dz2, c->nx, c->ny);
     // layer 2
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a1, c->dz2, c->nx, c->ny, c->part);
-    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
-                       grads + LAYER_P);
+    reduce_wgrad(c, nwblk, grads + LAYER_P, st);
     hipLaunchKernelGGL(k_cl_conv<2>, gc, dim3(256), 0, st, c->dz2, c->wt + LAYER_W, nullptr, c->a1, c->dz1,
                        c->nx, c->ny);
     // layer 1
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->x0, c->dz1, c->nx, c->ny, c->part);
-    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->part, nwblk,
-                       grads);
+    reduce_wgrad(c, nwblk, grads, st);
     rc = ck(hipGetLastError());
     if (rc != PLBM_OK || !loss) return rc;
     const int nl = (int)(gn.x * gn.y * gn.z);
