@@ -69,6 +69,9 @@ def parse():
                     help="training iterations of the learned closure (0 skips it)")
     ap.add_argument("--closure-train-seeds", type=int, default=100)
     ap.add_argument("--closure-held-seeds", type=int, default=10)
+    ap.add_argument("--q9-forms", default="q9f64,q9f32",
+                    help="D2Q9 isothermal (zeta = 4) forms timed beside the D2Q25 ones "
+                         "(empty: none)")
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure experiment")
     return ap.parse_args()
@@ -79,7 +82,12 @@ def log(msg):
 
 
 def make_lattice(storage, n, fields, theta):
+    """D2Q25 lattice of the given storage, or for "q9f64" / "q9f32" the
+    isothermal D2Q9 lattice of the three-velocity family with zeta = 4
+    (theta0 = 1/4; the theta field is not used)."""
     from paper_1402_5487_amd.lattice import Lattice
+    if storage.startswith("q9"):
+        return Lattice(2, n, n, omega=1.8, storage=storage[2:], zeta=4.0).init(*fields)
     return Lattice(2, n, n, omega=1.8, storage=storage, theta0=theta).init(*fields)
 
 
@@ -253,6 +261,11 @@ def main():
         print(json.dumps({"form": args.only, **results[args.only]}), flush=True)
         return
 
+    d2q9 = {}
+    for storage in [f for f in args.q9_forms.split(",") if f]:
+        log(f"timing {storage} {n}x{n} steps={args.steps} warmup={args.warmup}")
+        d2q9[storage] = time_form(storage, n, fields, args.steps, args.warmup, args.theta)
+
     acc = accuracy(forms, n, fields, args.accuracy_steps, args.theta) \
         if args.accuracy_steps > 0 else {}
     for k, v in acc.items():
@@ -308,6 +321,7 @@ def main():
         "forms": rnd(results),
         "vs_fp64_speedup": round(h["mlups"] / results["f64"]["mlups"], 3)
         if "f64" in results else None,
+        "d2q9": rnd(d2q9) if d2q9 else None,
         "batch": rnd(batch) if batch else None,
         "closure": rnd(closure) if closure else None,
         "copy_gbs": round(copy_gbs, 1),

@@ -36,6 +36,7 @@ def _load():
     lib.ref_weights_1d.restype = None
     lib.ref_init.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D]
     lib.ref_step.argtypes = [i, i, i, i, _D, _D, d, i, _D, i, i]
+    lib.ref_step_theta0.argtypes = [i, i, i, i, _D, _D, d, i, d, _D, i, i]
     lib.ref_moments.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, i]
     lib.ref_sums.argtypes = [i, i, i, i, _D, _D, _D]
     lib.ref_num_threads.argtypes = []
@@ -90,11 +91,15 @@ def weights_1d(c, u, theta):
 
 
 class Lattice:
-    """A D1Q5 (dim 1) or D2Q25 (dim 2, tensor product) lattice in FP64.
+    """A lattice in FP64 with the 1D velocities v (D1Q5 by default; dim 2 is
+    the tensor product).
 
-    bc: 0 periodic, 1 zero-gradient ghost ends (1D only)."""
+    bc: 0 periodic, 1 zero-gradient ghost ends (1D only).
+    theta0: None for the thermal model (the equilibrium at the local
+    temperature), or the fixed reference temperature of the isothermal
+    models (Sec. 2.3, Eq. 1d3v: mu_2 = theta0 + u^2)."""
 
-    def __init__(self, dim, nx, ny=1, v=V_D1Q5, omega=1.0, bc=0, c=None):
+    def __init__(self, dim, nx, ny=1, v=V_D1Q5, omega=1.0, bc=0, c=None, theta0=None):
         self.dim, self.nx, self.ny = int(dim), int(nx), int(ny)
         self.v = _f64(v)
         self.q1d = self.v.size
@@ -102,6 +107,7 @@ class Lattice:
         self.c = lagrange_coeffs(self.v) if c is None else _f64(c)
         self.omega = float(omega)
         self.bc = int(bc)
+        self.theta0 = None if theta0 is None else float(theta0)
 
     @property
     def shape(self):
@@ -113,6 +119,8 @@ class Lattice:
         """f(x, 0) = f_eq(rho, u, theta)(x)  (Eq. eqdist)."""
         f = np.zeros(self.shape)
         uy = np.zeros_like(_f64(rho)) if uy is None else uy
+        if self.theta0 is not None:            # isothermal: f_eq at theta0
+            theta = np.full(np.shape(rho), self.theta0)
         rc = _load().ref_init(self.dim, self.nx, self.ny, self.q1d, _p(self.v),
                               _p(self.c), _p(_f64(rho)), _p(_f64(ux)),
                               _p(_f64(uy)), _p(_f64(theta)), _p(f))
@@ -123,9 +131,10 @@ class Lattice:
     def step(self, f, nsteps=1, reverse_sums=False):
         """nsteps applications of Eq. srt (push form); returns a new array."""
         g = _f64(f).copy()
-        rc = _load().ref_step(self.dim, self.nx, self.ny, self.q1d, _p(self.v),
-                              _p(self.c), self.omega, self.bc, _p(g),
-                              int(nsteps), 1 if reverse_sums else 0)
+        rc = _load().ref_step_theta0(self.dim, self.nx, self.ny, self.q1d, _p(self.v),
+                                     _p(self.c), self.omega, self.bc,
+                                     0.0 if self.theta0 is None else self.theta0, _p(g),
+                                     int(nsteps), 1 if reverse_sums else 0)
         if rc != 0:
             raise ValueError("ref_step rejected its arguments")
         return g

@@ -225,9 +225,24 @@ int ref_init(int dim, int nx, int ny, int q1d, const double *vel,
  * Eq. srt in push form: collide every node into a post-collision array, then
  * move population k of node x to node x + v_k.  bc: 0 periodic, 1
  * zero-gradient ghost ends (1D only). */
+int ref_step_theta0(int dim, int nx, int ny, int q1d, const double *vel,
+                    const double *c, double omega, int bc, double theta0,
+                    double *f, int nsteps, int flags);
+
 int ref_step(int dim, int nx, int ny, int q1d, const double *vel,
              const double *c, double omega, int bc, double *f, int nsteps,
              int flags)
+{
+    return ref_step_theta0(dim, nx, ny, q1d, vel, c, omega, bc, 0.0, f, nsteps, flags);
+}
+
+/* As ref_step; with theta0 > 0 the equilibrium is taken at the fixed
+ * reference temperature theta0 instead of the local one: the isothermal
+ * models of Sec. 2.3 (Eq. 1d3v, Table 3vel), whose second Maxwell moment is
+ * mu_2 = theta0 + u^2. */
+int ref_step_theta0(int dim, int nx, int ny, int q1d, const double *vel,
+                    const double *c, double omega, int bc, double theta0,
+                    double *f, int nsteps, int flags)
 {
     int shift[REF_MAXQ];
     if (check_args(dim, nx, ny, q1d, vel, shift)) return -1;
@@ -250,6 +265,7 @@ int ref_step(int dim, int nx, int ny, int q1d, const double *vel,
                 for (int k = 0; k < q; ++k) fk[k] = f[k * n + p];
                 double rho, ux, uy, theta;
                 node_moments(dim, q1d, vel, fk, flags, &rho, &ux, &uy, &theta);
+                if (theta0 > 0.0) theta = theta0;
                 node_equilibrium(dim, q1d, c, rho, ux, uy, theta, feq);
                 for (int k = 0; k < q; ++k)
                     post[k * n + p] = (1.0 - omega) * fk[k] + omega * feq[k];

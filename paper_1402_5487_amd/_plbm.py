@@ -122,6 +122,22 @@ def desc_default(dim, nx, ny, omega, storage):
     return d
 
 
+def desc_q9(nx, ny, omega, storage, zeta=3.0, a=1):
+    """Descriptor of the isothermal three-velocity family in 2D (D2Q9, the
+    tensor product of Eq. 1d3v): velocities (0, +a, -a), reference
+    temperature theta0 = a^2 / zeta, table from plbm_coeffs."""
+    d = desc_default(2, nx, ny, omega, storage)
+    v = [0.0, float(a), -float(a)]
+    c = coeffs(v)
+    d.q1d = 3
+    for i in range(len(d.v)):
+        d.v[i] = v[i] if i < 3 else 0.0
+    for i in range(len(d.c)):
+        d.c[i] = c[i // 3][i % 3] if i < 9 else 0.0
+    d.theta0 = float(a) * float(a) / float(zeta)
+    return d
+
+
 def buffer_elems(d):
     return int(lib.plbm_buffer_elems(ctypes.byref(d)))
 

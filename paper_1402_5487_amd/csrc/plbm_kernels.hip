@@ -458,9 +458,17 @@ __global__ __launch_bounds__(256) void k_stream_copy(const CopyVec *__restrict__
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+namespace plbm {
+void note_hip_error(const char *what, int code)
+{
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (%d)", what, code);
+}
+} // namespace plbm
+
 extern "C" int plbm_init(const plbm_desc *d, const double *rho, const double *ux,
                          const double *uy, const double *theta, void *f, void *stream)
 {
+    if (d && d->q1d == 3 && d->dim == 2) return plbm::q9_init(d, rho, ux, uy, f, stream);
     KParams p;
     int rc = make_params(d, p);
     if (rc != PLBM_OK) return rc;
@@ -471,6 +479,7 @@ extern "C" int plbm_init(const plbm_desc *d, const double *rho, const double *ux
 extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums,
                          void *stream)
 {
+    if (d && d->q1d == 3 && d->dim == 2) return plbm::q9_step(d, f_a, f_b, nsteps, sums, stream);
     KParams p;
     int rc = make_params(d, p);
     if (rc != PLBM_OK) return rc;
@@ -485,6 +494,8 @@ extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, d
 extern "C" int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
                             double *uy, double *theta, double *sums, void *stream)
 {
+    if (d && d->q1d == 3 && d->dim == 2)
+        return plbm::q9_moments(d, f, rho, ux, uy, theta, sums, stream);
     KParams p;
     int rc = make_params(d, p);
     if (rc != PLBM_OK) return rc;

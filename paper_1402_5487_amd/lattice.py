@@ -19,16 +19,23 @@ def _dev_f64(a, device):
 
 
 class Lattice:
-    """D1Q5 (dim 1, zero-gradient ends) or D2Q25 (dim 2, periodic) lattice.
+    """D1Q5 (dim 1, zero-gradient ends) or D2Q25 (dim 2, periodic) lattice of
+    the thermal five-velocity model, or (zeta given, dim 2) the isothermal
+    D2Q9 lattice of the three-velocity family with theta0 = 1 / zeta.
 
     storage: "f64", "f32", "f16dev" or "bf16dev" (16-bit deviations from the
-    rest state rho0 w_k with per-plane power-of-two scales; 2D only).
+    rest state rho0 w_k with per-plane power-of-two scales; D2Q25 only).
     """
 
     def __init__(self, dim, nx, ny=1, omega=1.0, storage="f64", device="cuda:0",
-                 rho0=1.0, theta0=None):
+                 rho0=1.0, theta0=None, zeta=None):
         self.device = torch.device(device)
-        self.desc = _plbm.desc_default(dim, nx, ny, omega, storage)
+        if zeta is not None:
+            if dim != 2:
+                raise ValueError("the three-velocity family is built in 2D")
+            self.desc = _plbm.desc_q9(nx, ny, omega, storage, zeta=zeta)
+        else:
+            self.desc = _plbm.desc_default(dim, nx, ny, omega, storage)
         if theta0 is not None:
             self.desc.theta0 = float(theta0)
         self.desc.rho0 = float(rho0)
@@ -54,7 +61,7 @@ class Lattice:
     def bytes_per_step(self):
         """Algorithmic HBM bytes of one step: every population read and
         written once."""
-        q = 5 if self.dim == 1 else 25
+        q = self.desc.q1d ** self.dim
         return 2 * q * self.nx * self.ny * _plbm.elem_bytes(self.desc)
 
     def _fields(self, rho, ux, uy, theta):

@@ -136,3 +136,28 @@ def test_strerror():
     assert _plbm.strerror(0) == "ok"
     assert "non-finite" in _plbm.strerror(_plbm.PLBM_ENONFINITE)
     assert _plbm.strerror(-99) == "unknown status"
+
+
+def test_three_velocity_family_descriptor_and_rejections():
+    """q1d = 3 (isothermal D2Q9): a valid descriptor sizes 9 populations per
+    node; 16-bit storage, 1D and asymmetric sets are refused before launch."""
+    d = _plbm.desc_q9(64, 32, 1.8, "f64", zeta=4.0)
+    assert d.q1d == 3 and abs(d.theta0 - 0.25) < 1e-15
+    assert _plbm.buffer_elems(d) == 9 * 64 * 32
+    buf = ctypes.c_void_p(16)         # never dereferenced: validation fails first
+    other = ctypes.c_void_p(32)
+    for change in ("f16", "dim1", "asym"):
+        e = _plbm.desc_q9(64, 32, 1.8, "f64", zeta=4.0)
+        if change == "f16":
+            e.storage = _plbm.PLBM_F16DEV
+            for k in range(9):
+                e.scale[k] = 1.0
+        elif change == "dim1":
+            e.dim, e.ny, e.bc = 1, 1, 1
+        else:
+            e.v[2] = -2.0
+            c = _plbm.coeffs([0.0, 1.0, -2.0])
+            for i in range(9):
+                e.c[i] = c[i // 3][i % 3]
+        rc = _plbm.lib.plbm_step(ctypes.byref(e), buf, other, 1, None, None)
+        assert rc == _plbm.PLBM_EUNSUPPORTED, (change, rc)

@@ -1,0 +1,136 @@
+"""Pins of the oracle's isothermal three-velocity family (Sec. 2.3, Eq. 1d3v,
+Table 3vel) and of its two-dimensional tensor product D2Q9 (Sec. 3.2)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1402_5487_amd import inputs
+
+
+@pytest.mark.parametrize("zeta", [3.0, 4.0, 5.0, 2.5])
+def test_rule_is_eq_1d3v(zeta):
+    """The Lagrange rule of {0, +-sqrt(zeta theta0)} with the isothermal
+    Maxwell moments (mu_2 = theta0 + u^2) is the closed form the paper prints:
+    r_i = w_i [1 + v_i u / theta0 + u^2 (v_i^2 - theta0) / ((zeta - 1) theta0^2)],
+    w_1 = 1 - 1/zeta, w_2,3 = 1/(2 zeta)."""
+    th0 = 0.3
+    a = np.sqrt(zeta * th0)
+    v = np.array([0.0, a, -a])
+    c = oracle.lagrange_coeffs(v)
+    w = np.array([1 - 1 / zeta, 1 / (2 * zeta), 1 / (2 * zeta)])
+    for u in (-0.2, -0.05, 0.0, 0.1, 0.3):
+        r = oracle.weights_1d(c, u, th0)
+        closed = w * (1 + v * u / th0 + u * u * (v * v - th0) / ((zeta - 1) * th0 * th0))
+        assert np.abs(r - closed).max() < 1e-14
+
+
+def test_zeta3_rest_weights_are_lbgk_d2q9():
+    """Table 3vel: zeta = 3 is the LBGK model; at rest its tensor product
+    has the D2Q9 weights 4/9, 1/9, 1/36."""
+    r = oracle.weights_1d(oracle.lagrange_coeffs([0, 1, -1]), 0.0, 1.0 / 3.0)
+    w2 = np.outer(r, r)
+    assert abs(w2[0, 0] - 4 / 9) < 1e-15
+    assert abs(w2[0, 1] - 1 / 9) < 1e-15 and abs(w2[1, 0] - 1 / 9) < 1e-15
+    assert abs(w2[1, 1] - 1 / 36) < 1e-15 and abs(w2[1, 2] - 1 / 36) < 1e-15
+
+
+def _iso_lattice(n, zeta, omega, ny=None):
+    return oracle.Lattice(2, n, n if ny is None else ny, v=[0, 1, -1], omega=omega,
+                          theta0=1.0 / zeta)
+
+
+@pytest.mark.parametrize("zeta", [3.0, 4.0])
+def test_isothermal_step_conserves_mass_and_momentum(zeta):
+    rng = np.random.default_rng(5)
+    n = 12
+    lat = _iso_lattice(n, zeta, 1.7)
+    f = lat.init(1 + 0.05 * rng.standard_normal((n, n)), 0.05 * rng.standard_normal((n, n)),
+                 0.05 * rng.standard_normal((n, n)), np.full((n, n), 1.0 / zeta))
+    s0 = lat.sums(f)
+    s1 = lat.sums(lat.step(f, 50))
+    assert abs(s1[0] - s0[0]) < 1e-12 * s0[0]
+    assert np.abs(s1[1:3] - s0[1:3]).max() < 1e-12 * s0[0]
+
+
+def test_isothermal_equilibrium_is_a_fixed_point_of_uniform_flow():
+    lat = _iso_lattice(6, 4.0, 1.3)
+    ones = np.ones((6, 6))
+    f = lat.init(ones, 0.07 * ones, -0.03 * ones, ones / 4.0)
+    assert np.abs(lat.step(f, 7) - f).max() < 1e-15
+
+
+@pytest.mark.parametrize("zeta,omega", [(3.0, 1.0), (4.0, 1.0), (3.0, 1.6), (4.0, 1.6)])
+def test_viscosity_of_the_family(zeta, omega):
+    """Shear wave u_x = U sin(2 pi y / L): amplitude decays as exp(-nu k^2 t)
+    with nu = (1/omega - 1/2) theta0 in lattice units, which is the paper's
+    (1/omega - 1/2) sqrt(theta0) dx / sqrt(zeta) for a = sqrt(zeta theta0) = 1."""
+    L, U, steps = 64, 1e-4, 200
+    lat = _iso_lattice(L, zeta, omega, ny=L)
+    f = lat.init(*inputs.shear_wave(L, L, amp=U, theta=1.0 / zeta))
+    y = np.arange(L)
+    s = np.sin(2 * np.pi * y / L)
+
+    def amp(g):
+        return (lat.moments(g)[1].mean(axis=1) * s).sum() / (s * s).sum()
+
+    a0 = amp(f)
+    a1 = amp(lat.step(f, steps))
+    k = 2 * np.pi / L
+    nu = -np.log(a1 / a0) / (k * k * steps)
+    nu_closed = (1 / omega - 0.5) / zeta
+    assert abs(nu / nu_closed - 1) < (2e-3 if omega == 1.0 else 2e-2)
+
+
+def test_viscosity_matched_omega_of_the_shear_layer_runs():
+    """Sec. 3.2: equal viscosity (1/omega - 1/2) sqrt(theta0) dx / sqrt(zeta)
+    for the LBGK at omega = 1.99880 and zeta = 4 gives the paper's 1.99862 to
+    its printed precision (the exact value is 1.998614)."""
+    w3 = 1.99880
+    w4 = 1.0 / (0.5 + (1 / w3 - 0.5) * np.sqrt(4.0) / np.sqrt(3.0))
+    assert abs(w4 - 1.99862) < 1e-5
+    # and the step counts of equal physical time: dt scales as 1/sqrt(zeta)
+    assert round(500 * np.sqrt(4.0 / 3.0)) == 577 and round(1500 * np.sqrt(4.0 / 3.0)) == 1732
+
+
+def _shear_layer(zeta, omega, steps):
+    """The paper's 128^2 shear layer (l0 = 80, eps = 0.05, u0 = 0.069 in LBGK
+    lattice units, scaled by sqrt(3/zeta) into this model's units); returns
+    (ux, uy) in LBGK units at each requested step."""
+    n, th0 = 128, 1.0 / zeta
+    s = np.sqrt(3.0 / zeta)
+    u0 = 0.069 * s
+    lat = _iso_lattice(n, zeta, omega)
+    f = lat.init(*inputs.kelvin_helmholtz(n, n, u0=u0, delta=n / 80.0, theta=th0,
+                                          uy_amp=0.05 * u0, phase=np.pi / 2))
+    out, t = {}, 0
+    for st in steps:
+        f = lat.step(f, st - t)
+        t = st
+        _, ux, uy, _ = lat.moments(f)
+        out[st] = (ux / s, uy / s)
+    return out
+
+
+def _high_k_share(ux, uy):
+    n = ux.shape[0]
+    spec = np.abs(np.fft.fft2(ux)) ** 2 + np.abs(np.fft.fft2(uy)) ** 2
+    k = np.abs(np.fft.fftfreq(n))
+    kk = np.maximum(k[:, None], k[None, :])
+    return spec[kk >= 0.25].sum() / spec.sum()
+
+
+def test_shear_layer_lbgk_and_zeta4_agree_and_zeta4_is_more_stable():
+    """Sec. 3.2: at equal physical time (LBGK step 500 = zeta-4 step 577) the
+    velocity amplitudes of the two models agree; later the LBGK run is taken
+    over by grid-scale noise well before the zeta-4 run (compared here at
+    LBGK step 900 = zeta-4 step 1039)."""
+    w3 = 1.99880
+    w4 = 1.0 / (0.5 + (1 / w3 - 0.5) * 2.0 / np.sqrt(3.0))
+    a = _shear_layer(3.0, w3, [500, 900])
+    b = _shear_layer(4.0, w4, [577, 1039])
+    m3 = np.hypot(*a[500])
+    m4 = np.hypot(*b[577])
+    assert np.linalg.norm(m3 - m4) / np.linalg.norm(m3) < 0.01
+    assert _high_k_share(*a[500]) < 1e-3 and _high_k_share(*b[577]) < 1e-3
+    h3, h4 = _high_k_share(*a[900]), _high_k_share(*b[1039])
+    assert h3 > 0.03 and h4 < 0.01 and h3 > 10 * h4, (h3, h4)
