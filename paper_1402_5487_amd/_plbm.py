@@ -122,11 +122,12 @@ def desc_default(dim, nx, ny, omega, storage):
     return d
 
 
-def desc_q9(nx, ny, omega, storage, zeta=3.0, a=1):
-    """Descriptor of the isothermal three-velocity family in 2D (D2Q9, the
-    tensor product of Eq. 1d3v): velocities (0, +a, -a), reference
-    temperature theta0 = a^2 / zeta, table from plbm_coeffs."""
-    d = desc_default(2, nx, ny, omega, storage)
+def desc_q3(dim, nx, ny, omega, storage, zeta=3.0, a=1):
+    """Descriptor of the isothermal three-velocity family (Eq. 1d3v): D1Q3
+    with zero-gradient ends (dim 1) or its tensor product D2Q9 (dim 2,
+    periodic); velocities (0, +a, -a), reference temperature
+    theta0 = a^2 / zeta, table from plbm_coeffs."""
+    d = desc_default(dim, nx, ny, omega, storage)
     v = [0.0, float(a), -float(a)]
     c = coeffs(v)
     d.q1d = 3

@@ -10,11 +10,12 @@ int validate(const plbm_desc *d);
 // Records a failed HIP call for plbm_last_hip_error (plbm_kernels.hip).
 void note_hip_error(const char *what, int code);
 
-// The isothermal three-velocity family (q1d = 3, dim 2), plbm_q9.hip; the
-// public plbm_init / plbm_step / plbm_moments forward to these.
-int q9_init(const plbm_desc *d, const double *rho, const double *ux, const double *uy, void *f,
+// The isothermal three-velocity family (q1d = 3: D1Q3 and its tensor product
+// D2Q9), plbm_q3.hip; the public plbm_init / plbm_step / plbm_moments forward
+// to these.
+int q3_init(const plbm_desc *d, const double *rho, const double *ux, const double *uy, void *f,
             void *stream);
-int q9_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, void *stream);
-int q9_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy,
+int q3_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, void *stream);
+int q3_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy,
                double *theta, double *sums, void *stream);
 } // namespace plbm

@@ -468,7 +468,7 @@ void note_hip_error(const char *what, int code)
 extern "C" int plbm_init(const plbm_desc *d, const double *rho, const double *ux,
                          const double *uy, const double *theta, void *f, void *stream)
 {
-    if (d && d->q1d == 3 && d->dim == 2) return plbm::q9_init(d, rho, ux, uy, f, stream);
+    if (d && d->q1d == 3) return plbm::q3_init(d, rho, ux, uy, f, stream);
     KParams p;
     int rc = make_params(d, p);
     if (rc != PLBM_OK) return rc;
@@ -479,7 +479,7 @@ extern "C" int plbm_init(const plbm_desc *d, const double *rho, const double *ux
 extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums,
                          void *stream)
 {
-    if (d && d->q1d == 3 && d->dim == 2) return plbm::q9_step(d, f_a, f_b, nsteps, sums, stream);
+    if (d && d->q1d == 3) return plbm::q3_step(d, f_a, f_b, nsteps, sums, stream);
     KParams p;
     int rc = make_params(d, p);
     if (rc != PLBM_OK) return rc;
@@ -494,8 +494,8 @@ extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, d
 extern "C" int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
                             double *uy, double *theta, double *sums, void *stream)
 {
-    if (d && d->q1d == 3 && d->dim == 2)
-        return plbm::q9_moments(d, f, rho, ux, uy, theta, sums, stream);
+    if (d && d->q1d == 3)
+        return plbm::q3_moments(d, f, rho, ux, uy, theta, sums, stream);
     KParams p;
     int rc = make_params(d, p);
     if (rc != PLBM_OK) return rc;

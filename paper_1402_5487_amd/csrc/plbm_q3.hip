@@ -1,6 +1,6 @@
-// libplbm device code for the isothermal three-velocity family in 2D: the
-// tensor product D2Q9 of the 1D rule of Eq. 1d3v (velocities {0, +a, -a},
-// a^2 = zeta theta0).  It is the Lagrange rule of Eq. rdr with the Maxwell
+// libplbm device code for the isothermal three-velocity family: the 1D rule
+// of Eq. 1d3v (velocities {0, +a, -a}, a^2 = zeta theta0) on D1Q3 lattices
+// with zero-gradient ends, and its tensor product D2Q9 on periodic lattices.  It is the Lagrange rule of Eq. rdr with the Maxwell
 // moments of a fixed reference temperature: mu_0 = 1, mu_1 = u,
 // mu_2 = theta0 + u^2, so for the symmetric set
 //   r_0 = 1 + c02 mu_2,   r_(+-a) = c12 mu_2 +- c11 mu_1
@@ -9,7 +9,8 @@
 // form, zeta = 4 the parametric model of Table 3vel.
 //
 // Same streaming design as the D2Q25 step: pull scheme with A/B buffers,
-// row-interleaved layout (y * 9 + k) * nx + x, one 256-node row segment per
+// row-interleaved layout (y * 9 + k) * nx + x (1D: k * (nx + 6) + x + 3, three
+// ghost nodes per end as for D1Q5), one 256-node row segment per
 // workgroup with XCD-contiguous tile numbering, a scalar row base per y
 // velocity plus a 32-bit lane offset per x velocity (the periodic wrap in x
 // folded into the offsets), non-temporal stores (and loads for 4- and
@@ -47,6 +48,7 @@ struct Rule3 {
 };
 
 struct Q9Params {
+    int dim;
     int nx, ny, tiles_x, ntiles;
     int sx[Q3];              // streaming shifts (0, +a, -a)
     Rule3<double> r64;
@@ -232,6 +234,94 @@ __global__ __launch_bounds__(TX) void k_moments_q9(const T *__restrict__ src, Q9
     if (partials) block_sums_store<4>(acc, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4);
 }
 
+// ---------------------------------------------------------------------------
+// D1Q3: padded layout k * (nx + 6) + x + 3.  Step: pull f_k = src_k(x - v_k),
+// relax to rho r(u), write at x; the ghost nodes at each end take the edge
+// node's post-collision populations (zero-gradient ends, as for D1Q5).
+// ---------------------------------------------------------------------------
+template <typename T, typename C, bool SUMS>
+__global__ __launch_bounds__(TX) void k_step_q3_1d(const T *__restrict__ src, T *__restrict__ dst, Q9Params p,
+                                                   double *__restrict__ partials)
+{
+    const Rule3<C> &R = rule_of<C>(p);
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const long long ps = (long long)p.nx + 2 * PLBM_GHOST;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (x < p.nx) {
+        C f[Q3];
+#pragma unroll
+        for (int k = 0; k < Q3; ++k) f[k] = (C)src[k * ps + x + PLBM_GHOST - p.sx[k]];
+        const C rho = f[0] + (f[1] + f[2]);
+        const C u = R.a * (f[1] - f[2]) / rho;
+        C r[Q3];
+        rule3<C>(u, R, r);
+        const C wr = R.omega * rho, keep = C(1) - R.omega;
+#pragma unroll
+        for (int k = 0; k < Q3; ++k) {
+            const T h = (T)fma(keep, f[k], wr * r[k]);
+            dst[k * ps + x + PLBM_GHOST] = h;
+            if (x == 0)
+                for (int g = 0; g < PLBM_GHOST; ++g) dst[k * ps + g] = h;
+            if (x == p.nx - 1)
+                for (int g = 0; g < PLBM_GHOST; ++g) dst[k * ps + p.nx + PLBM_GHOST + g] = h;
+            if constexpr (SUMS) {
+                const double vk = (double)p.sx[k];
+                acc[0] += (double)h;
+                acc[1] += (double)h * vk;
+                acc[3] += (double)h * vk * vk;
+            }
+        }
+    }
+    if constexpr (SUMS) block_sums_store<4>(acc, partials + (size_t)blockIdx.x * 4);
+}
+
+// Padded index q holds node y = q - 3; population k there is f_eq_k of node
+// y + v_k (clamped into the lattice), so the pull at y + v_k returns f_eq.
+template <typename T>
+__global__ __launch_bounds__(TX) void k_init_q3_1d(const double *__restrict__ rho, const double *__restrict__ ux,
+                                                   T *__restrict__ dst, Q9Params p)
+{
+    const int q = blockIdx.x * TX + threadIdx.x;
+    const long long ps = (long long)p.nx + 2 * PLBM_GHOST;
+    if (q >= ps) return;
+    const int y = q - PLBM_GHOST;
+#pragma unroll
+    for (int k = 0; k < Q3; ++k) {
+        int s = y + p.sx[k];
+        s = s < 0 ? 0 : (s >= p.nx ? p.nx - 1 : s);
+        double r[Q3];
+        rule3<double>(ux[s], p.r64, r);
+        dst[k * ps + q] = (T)(rho[s] * r[k]);
+    }
+}
+
+// rho, u and rho theta = sum f (v - u)^2 (one dimension) of the pulled state.
+template <typename T>
+__global__ __launch_bounds__(TX) void k_moments_q3_1d(const T *__restrict__ src, Q9Params p, double *__restrict__ rho,
+                                                      double *__restrict__ ux, double *__restrict__ th,
+                                                      double *__restrict__ partials)
+{
+    const int x = blockIdx.x * TX + threadIdx.x;
+    const long long ps = (long long)p.nx + 2 * PLBM_GHOST;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (x < p.nx) {
+        double f[Q3];
+#pragma unroll
+        for (int k = 0; k < Q3; ++k) f[k] = (double)src[k * ps + x + PLBM_GHOST - p.sx[k]];
+        const double r = f[0] + (f[1] + f[2]);
+        const double j = p.r64.a * (f[1] - f[2]);
+        const double e = p.r64.a2 * (f[1] + f[2]);
+        const double u = j / r;
+        if (rho) rho[x] = r;
+        if (ux) ux[x] = u;
+        if (th) th[x] = e / r - u * u;
+        acc[0] = r;
+        acc[1] = j;
+        acc[3] = e;
+    }
+    if (partials) block_sums_store<4>(acc, partials + (size_t)blockIdx.x * 4);
+}
+
 int q9_hip(hipError_t e)
 {
     if (e == hipSuccess) return PLBM_OK;
@@ -249,7 +339,7 @@ int q9_params(const plbm_desc *d, Q9Params &p)
     const int rc = plbm::validate(d);
     if (rc != PLBM_OK) return rc;
     if (d->q1d != Q3) return PLBM_EINVAL;
-    if (d->dim != 2 || (d->storage != PLBM_F64 && d->storage != PLBM_F32)) return PLBM_EUNSUPPORTED;
+    if (d->storage != PLBM_F64 && d->storage != PLBM_F32) return PLBM_EUNSUPPORTED;
     if (!(d->theta0 > 0.0) || !std::isfinite(d->theta0)) return PLBM_EINVAL;
     const double a = d->v[1];
     if (d->v[0] != 0.0 || !(a > 0.0) || d->v[2] != -a) return PLBM_EUNSUPPORTED;
@@ -261,6 +351,7 @@ int q9_params(const plbm_desc *d, Q9Params &p)
                      near(c11, 0.5 / a) && near(c12, 0.5 / (a * a));
     if (!sym) return PLBM_EUNSUPPORTED;
     std::memset(&p, 0, sizeof(p));
+    p.dim = d->dim;
     p.nx = d->nx;
     p.ny = d->ny;
     p.tiles_x = (d->nx + TX - 1) / TX;
@@ -288,25 +379,36 @@ int q9_finish_sums(double *dev, int nblocks, double *host, hipStream_t st)
     return PLBM_OK;
 }
 
+template <typename T, typename C, bool SUMS>
+void q3_launch(const Q9Params &p, const T *src, T *dst, double *part, hipStream_t st)
+{
+    if (p.dim == 2) {
+        const size_t lds = sizeof(T) == 8 ? PLBM_Q9_LDS_F64 : PLBM_Q9_LDS_F32;
+        hipLaunchKernelGGL((k_step_q9<T, C, SUMS>), dim3(p.ntiles), dim3(TX), lds, st, src, dst, p, part);
+    } else {
+        hipLaunchKernelGGL((k_step_q3_1d<T, C, SUMS>), dim3(p.tiles_x), dim3(TX), 0, st, src, dst, p, part);
+    }
+}
+
 template <typename T, typename C>
 int q9_run(const Q9Params &p, void *fa, void *fb, int nsteps, double *sums, hipStream_t st)
 {
-    const size_t lds = sizeof(T) == 8 ? PLBM_Q9_LDS_F64 : PLBM_Q9_LDS_F32;
+    const int nblocks = p.dim == 2 ? p.ntiles : p.tiles_x;
     for (int s = 0; s < nsteps; ++s) {
         const T *src = static_cast<const T *>((s & 1) ? fb : fa);
         T *dst = static_cast<T *>((s & 1) ? fa : fb);
         (void)hipGetLastError();
         if (s == nsteps - 1 && sums) {
             double *part = nullptr;
-            int rc = q9_hip(hipMallocAsync((void **)&part, ((size_t)p.ntiles + 1) * 4 * sizeof(double), st));
+            int rc = q9_hip(hipMallocAsync((void **)&part, ((size_t)nblocks + 1) * 4 * sizeof(double), st));
             if (rc != PLBM_OK) return rc;
-            hipLaunchKernelGGL((k_step_q9<T, C, true>), dim3(p.ntiles), dim3(TX), lds, st, src, dst, p, part);
+            q3_launch<T, C, true>(p, src, dst, part, st);
             rc = q9_launch_status();
-            if (rc == PLBM_OK) rc = q9_finish_sums(part, p.ntiles, sums, st);
+            if (rc == PLBM_OK) rc = q9_finish_sums(part, nblocks, sums, st);
             (void)hipFreeAsync(part, st);
             return rc;
         }
-        hipLaunchKernelGGL((k_step_q9<T, C, false>), dim3(p.ntiles), dim3(TX), lds, st, src, dst, p, nullptr);
+        q3_launch<T, C, false>(p, src, dst, nullptr, st);
         const int rc = q9_launch_status();
         if (rc != PLBM_OK) return rc;
     }
@@ -317,15 +419,23 @@ int q9_run(const Q9Params &p, void *fa, void *fb, int nsteps, double *sums, hipS
 
 namespace plbm {
 
-int q9_init(const plbm_desc *d, const double *rho, const double *ux, const double *uy, void *f, void *stream)
+int q3_init(const plbm_desc *d, const double *rho, const double *ux, const double *uy, void *f, void *stream)
 {
     Q9Params p;
     const int rc = q9_params(d, p);
     if (rc != PLBM_OK) return rc;
-    if (!rho || !ux || !uy || !f) return PLBM_EINVAL;
+    if (!rho || !ux || !f || (p.dim == 2 && !uy)) return PLBM_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const dim3 g((p.nx + TX - 1) / TX, p.ny);
     (void)hipGetLastError();
+    if (p.dim == 1) {
+        const dim3 g((unsigned)((p.nx + 2 * PLBM_GHOST + TX - 1) / TX));
+        if (d->storage == PLBM_F64)
+            hipLaunchKernelGGL(k_init_q3_1d<double>, g, dim3(TX), 0, st, rho, ux, (double *)f, p);
+        else
+            hipLaunchKernelGGL(k_init_q3_1d<float>, g, dim3(TX), 0, st, rho, ux, (float *)f, p);
+        return q9_launch_status();
+    }
+    const dim3 g((p.nx + TX - 1) / TX, p.ny);
     if (d->storage == PLBM_F64)
         hipLaunchKernelGGL(k_init_q9<double>, g, dim3(TX), 0, st, rho, ux, uy, (double *)f, p);
     else
@@ -333,19 +443,19 @@ int q9_init(const plbm_desc *d, const double *rho, const double *ux, const doubl
     return q9_launch_status();
 }
 
-int q9_step(const plbm_desc *d, void *fa, void *fb, int nsteps, double *sums, void *stream)
+int q3_step(const plbm_desc *d, void *fa, void *fb, int nsteps, double *sums, void *stream)
 {
     Q9Params p;
     const int rc = q9_params(d, p);
     if (rc != PLBM_OK) return rc;
     if (!fa || !fb || fa == fb || nsteps < 0) return PLBM_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (nsteps == 0) return sums ? q9_moments(d, fa, nullptr, nullptr, nullptr, nullptr, sums, stream) : PLBM_OK;
+    if (nsteps == 0) return sums ? q3_moments(d, fa, nullptr, nullptr, nullptr, nullptr, sums, stream) : PLBM_OK;
     if (d->storage == PLBM_F64) return q9_run<double, double>(p, fa, fb, nsteps, sums, st);
     return q9_run<float, float>(p, fa, fb, nsteps, sums, st);
 }
 
-int q9_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy, double *theta,
+int q3_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy, double *theta,
                double *sums, void *stream)
 {
     Q9Params p;
@@ -361,10 +471,18 @@ int q9_moments(const plbm_desc *d, const void *f, double *rho, double *ux, doubl
         if (rc != PLBM_OK) return rc;
     }
     (void)hipGetLastError();
-    if (d->storage == PLBM_F64)
+    if (p.dim == 1) {
+        if (d->storage == PLBM_F64)
+            hipLaunchKernelGGL(k_moments_q3_1d<double>, g, dim3(TX), 0, st, (const double *)f, p, rho, ux, theta,
+                               part);
+        else
+            hipLaunchKernelGGL(k_moments_q3_1d<float>, g, dim3(TX), 0, st, (const float *)f, p, rho, ux, theta,
+                               part);
+    } else if (d->storage == PLBM_F64) {
         hipLaunchKernelGGL(k_moments_q9<double>, g, dim3(TX), 0, st, (const double *)f, p, rho, ux, uy, theta, part);
-    else
+    } else {
         hipLaunchKernelGGL(k_moments_q9<float>, g, dim3(TX), 0, st, (const float *)f, p, rho, ux, uy, theta, part);
+    }
     rc = q9_launch_status();
     if (rc == PLBM_OK && sums) rc = q9_finish_sums(part, nblocks, sums, st);
     if (part) (void)hipFreeAsync(part, st);

@@ -20,7 +20,7 @@ def _dev_f64(a, device):
 
 class Lattice:
     """D1Q5 (dim 1, zero-gradient ends) or D2Q25 (dim 2, periodic) lattice of
-    the thermal five-velocity model, or (zeta given, dim 2) the isothermal
+    the thermal five-velocity model, or (zeta given) the isothermal D1Q3 /
     D2Q9 lattice of the three-velocity family with theta0 = 1 / zeta.
 
     storage: "f64", "f32", "f16dev" or "bf16dev" (16-bit deviations from the
@@ -31,9 +31,7 @@ class Lattice:
                  rho0=1.0, theta0=None, zeta=None):
         self.device = torch.device(device)
         if zeta is not None:
-            if dim != 2:
-                raise ValueError("the three-velocity family is built in 2D")
-            self.desc = _plbm.desc_q9(nx, ny, omega, storage, zeta=zeta)
+            self.desc = _plbm.desc_q3(dim, nx, ny, omega, storage, zeta=zeta)
         else:
             self.desc = _plbm.desc_default(dim, nx, ny, omega, storage)
         if theta0 is not None:

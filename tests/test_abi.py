@@ -140,24 +140,28 @@ def test_strerror():
 
 def test_three_velocity_family_descriptor_and_rejections():
     """q1d = 3 (isothermal D2Q9): a valid descriptor sizes 9 populations per
-    node; 16-bit storage, 1D and asymmetric sets are refused before launch."""
-    d = _plbm.desc_q9(64, 32, 1.8, "f64", zeta=4.0)
+    node; 16-bit storage and asymmetric sets are refused before launch, and a
+    1D descriptor must keep its zero-gradient ends."""
+    d = _plbm.desc_q3(2, 64, 32, 1.8, "f64", zeta=4.0)
     assert d.q1d == 3 and abs(d.theta0 - 0.25) < 1e-15
     assert _plbm.buffer_elems(d) == 9 * 64 * 32
     buf = ctypes.c_void_p(16)         # never dereferenced: validation fails first
     other = ctypes.c_void_p(32)
     for change in ("f16", "dim1", "asym"):
-        e = _plbm.desc_q9(64, 32, 1.8, "f64", zeta=4.0)
+        e = _plbm.desc_q3(2, 64, 32, 1.8, "f64", zeta=4.0)
         if change == "f16":
             e.storage = _plbm.PLBM_F16DEV
             for k in range(9):
                 e.scale[k] = 1.0
         elif change == "dim1":
-            e.dim, e.ny, e.bc = 1, 1, 1
+            e.dim, e.ny, e.bc = 1, 1, 0
         else:
             e.v[2] = -2.0
             c = _plbm.coeffs([0.0, 1.0, -2.0])
             for i in range(9):
                 e.c[i] = c[i // 3][i % 3]
         rc = _plbm.lib.plbm_step(ctypes.byref(e), buf, other, 1, None, None)
-        assert rc == _plbm.PLBM_EUNSUPPORTED, (change, rc)
+        want = _plbm.PLBM_EINVAL if change == "dim1" else _plbm.PLBM_EUNSUPPORTED
+        assert rc == want, (change, rc)
+    d1 = _plbm.desc_q3(1, 1000, 1, 0.93, "f64", zeta=4.0)
+    assert _plbm.buffer_elems(d1) == 3 * (1000 + 6)

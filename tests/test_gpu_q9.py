@@ -112,3 +112,41 @@ def test_full_size_sampled_nodes(storage):
         post = one.step(pre, 1).ravel()
         got = np.array([dst[k, y, x].double().item() for k in range(9)])
         assert np.abs(got - post).max() < tol * np.abs(post).max(), (y, x)
+
+
+# --------------------------------------------------------------------------
+# D1Q3 (dim 1, zero-gradient ends)
+# --------------------------------------------------------------------------
+
+def _run_1d(n, zeta, omega, steps, fields, storage="f64"):
+    lat = Lattice(1, n, omega=omega, storage=storage, zeta=zeta).init(*fields)
+    lat.step(steps)
+    got = [None if t is None else t.cpu().numpy() for t in lat.moments()]
+    ref_lat = oracle.Lattice(1, n, v=list(V3), omega=omega, bc=1, theta0=1.0 / zeta)
+    f = ref_lat.step(ref_lat.init(*fields), steps)
+    return got, ref_lat.moments(f)
+
+
+def test_d1q3_shock_tube_f64_matches_oracle():
+    """The paper's rho_L / rho_R = 6 shock tube with zeta = 4 (418 steps)."""
+    th0 = 0.25
+    fields = inputs.shock_tube(1000, rho_l=6.0, theta_l=th0, rho_r=1.0, theta_r=th0)
+    got, ref = _run_1d(1000, 4.0, 4 * np.sqrt(3) - 6, 418, fields)
+    assert rel_err(got[0], ref[0]) < 1e-12
+    assert rel_err(got[1], ref[1], 0.5) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 257])
+def test_d1q3_tiny_and_ragged(n):
+    rng = np.random.default_rng(n)
+    fields = (1 + 0.05 * rng.standard_normal(n), 0.05 * rng.standard_normal(n), None,
+              np.full(n, 1 / 3))
+    got, ref = _run_1d(n, 3.0, 1.3, 30, fields)
+    assert rel_err(got[0], ref[0]) < 1e-12 and rel_err(got[1], ref[1], 0.05) < 1e-12
+
+
+def test_d1q3_f32_matches_oracle():
+    th0 = 0.25
+    fields = inputs.shock_tube(1000, rho_l=1.1, theta_l=th0, rho_r=1.0, theta_r=th0)
+    got, ref = _run_1d(1000, 4.0, 1.0, 200, fields, storage="f32")
+    assert rel_err(got[0], ref[0]) < 200 * 50 * EPS32

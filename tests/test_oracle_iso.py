@@ -134,3 +134,45 @@ def test_shear_layer_lbgk_and_zeta4_agree_and_zeta4_is_more_stable():
     assert _high_k_share(*a[500]) < 1e-3 and _high_k_share(*b[577]) < 1e-3
     h3, h4 = _high_k_share(*a[900]), _high_k_share(*b[1039])
     assert h3 > 0.03 and h4 < 0.01 and h3 > 10 * h4, (h3, h4)
+
+
+def _shock_tube_q3(zeta, omega, steps, n=1000, rho_l=6.0, rho_r=1.0):
+    """Sec. 3.2 shock tube on D1Q3: left half rho_L, right half rho_R, at
+    rest, theta = theta0 = 1/zeta; returns (rho, u / sqrt(theta0))."""
+    th0 = 1.0 / zeta
+    lat = oracle.Lattice(1, n, v=[0, 1, -1], omega=omega, bc=1, theta0=th0)
+    rho, ux, _, _ = inputs.shock_tube(n, rho_l=rho_l, theta_l=th0, rho_r=rho_r, theta_r=th0)
+    f = lat.step(lat.init(rho, ux, None, np.full(n, th0)), steps)
+    r, u, _, _ = lat.moments(f)
+    return r, u / np.sqrt(th0)
+
+
+def test_d1q3_zeta4_shock_tube_matches_exact_and_paper():
+    """Sec. 3.2: rho_L / rho_R = 6, zeta = 4 at omega = 4 sqrt 3 - 6 (viscosity
+    of the LBGK at omega = 1), 418 iterations.  The isothermal exact Riemann
+    solution (gamma = 1; p*/p_R = 2.41 as in Table Rankine) gives the plateau
+    velocity and the shock position; the paper marks u = 0.91 and x = 826
+    (nodes numbered from 1)."""
+    from oracle import riemann
+    steps = 418
+    r, u = _shock_tube_q3(4.0, 4 * np.sqrt(3) - 6, steps)
+    s = riemann.star_state(6.0, 0.0, 6.0, 1.0, 0.0, 1.0, 1.0)
+    assert abs(s.p - 2.41) < 0.005
+    plateau = u[700:760]
+    assert abs(plateau.mean() / s.u - 1) < 2e-3 and plateau.std() < 1e-3
+    assert abs(plateau.mean() - 0.91) < 0.005
+    speed = s.u * s.rho_r / (s.rho_r - 1.0) * np.sqrt(0.25)      # nodes per step
+    mid = 0.5 * (s.rho_r + 1.0)
+    i = int(np.where(r[600:] < mid)[0][0]) + 600
+    front = i - 1 + (r[i - 1] - mid) / (r[i - 1] - r[i])
+    assert abs(front - (499.5 + speed * steps)) < 1.5
+    assert abs((front + 1) - 826) < 3
+    # monotone profile: total variation of the exact solution is 2 u*
+    assert np.abs(np.diff(u)).sum() < 1.02 * 2 * s.u
+
+
+def test_d1q3_lbgk_shock_tube_oscillates():
+    """Sec. 3.2: the LBGK model (zeta = 3, omega = 1, 362 iterations, the same
+    physical time) gives an oscillating profile for the same shock tube."""
+    _, u = _shock_tube_q3(3.0, 1.0, 362)
+    assert np.abs(np.diff(u)).sum() > 10 * 2 * 0.9103
