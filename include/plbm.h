@@ -309,11 +309,13 @@ int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, const float *in
  * plbm_closure_forward -- run the network on `frames` post-collision buffers
  * (post: host array of device pointers, each a population buffer of the
  * coarse lattice in its storage type) with parameters `params` (device,
- * PLBM_CNN_PARAMS floats).  Keeps the activations for plbm_closure_backward
- * and plbm_closure_apply.
+ * PLBM_CNN_PARAMS floats).  noise: NULL, or device FP32 values added, times
+ * noise_amp, to the normalised input, laid out [frame][y][x][k] (training
+ * augmentation; the caller draws them).  Keeps the activations for
+ * plbm_closure_backward and plbm_closure_apply.
  */
 int plbm_closure_forward(plbm_closure *c, const float *params, const void *const *post,
-                         int frames, void *stream);
+                         int frames, const float *noise, float noise_amp, void *stream);
 
 /*
  * plbm_closure_backward -- moment-form loss of the last forward pass and its

@@ -241,7 +241,8 @@ def _setup_closure(lib):
     lib.plbm_closure_create.argtypes = [P, ctypes.c_int, ctypes.POINTER(vp)]
     lib.plbm_closure_destroy.argtypes = [vp]
     lib.plbm_closure_set_norm.argtypes = [vp, F, F, F, F]
-    lib.plbm_closure_forward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.plbm_closure_forward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_float,
+                                         vp]
     lib.plbm_closure_backward.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.c_float, vp,
                                           ctypes.POINTER(ctypes.c_double), vp]
     lib.plbm_closure_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,

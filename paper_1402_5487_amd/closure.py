@@ -78,11 +78,17 @@ class Closure:
             raise ValueError("set_norm: 25, 25, 25 and 4 values expected")
         _plbm.check(_plbm.lib.plbm_closure_set_norm(self.handle, *arr), "plbm_closure_set_norm")
 
-    def forward(self, params, posts):
+    def forward(self, params, posts, noise=None, noise_amp=0.0):
+        """noise: None, or a float32 device tensor of frames * ny * nx * 25
+        values added (times noise_amp) to the normalised input."""
         self._nf = len(posts)
-        _plbm.check(_plbm.lib.plbm_closure_forward(self.handle, ctypes.c_void_p(params.data_ptr()),
-                                                   _ptrs(posts), len(posts), _stream(self.device)),
-                    "plbm_closure_forward")
+        if noise is not None and (noise.dtype != torch.float32 or
+                                  noise.numel() < len(posts) * self.ny * self.nx * 25):
+            raise ValueError("forward: float32 noise of frames * ny * nx * 25 values expected")
+        _plbm.check(_plbm.lib.plbm_closure_forward(
+            self.handle, ctypes.c_void_p(params.data_ptr()), _ptrs(posts), len(posts),
+            None if noise is None else ctypes.c_void_p(noise.data_ptr()), float(noise_amp),
+            _stream(self.device)), "plbm_closure_forward")
 
     def backward(self, params, targets, grads, want_loss=True, reg=0.0):
         """targets: per frame, the increment error d as a float32 (4, ny, nx)

@@ -112,7 +112,11 @@ class Experiment:
         self.net.set_norm(*self.norm)
 
     # -- training --------------------------------------------------------
-    def train(self, iters, lr=1e-3, seed=0, log_every=0):
+    def train(self, iters, lr=1e-3, seed=0, log_every=0, input_noise=0.0):
+        """Adam on random batches of frames; input_noise > 0 adds Gaussian
+        noise of that standard deviation to the normalised inputs (the
+        targets stay), which penalises the network's sensitivity to its
+        input."""
         if self.params is None:
             self.params = init_params(seed, self.device)
         p = self.params
@@ -120,10 +124,17 @@ class Experiment:
         m = torch.zeros_like(p)
         v = torch.zeros_like(p)
         rng = random.Random(seed)
+        gen = torch.Generator(device=self.device).manual_seed(seed + 1)
+        noise = None
+        if input_noise > 0:
+            noise = torch.empty(self.batch * self.nc * self.nc * 25, dtype=torch.float32,
+                                device=self.device)
         hist = []
         for it in range(1, iters + 1):
             idx = [rng.randrange(len(self.frames)) for _ in range(self.batch)]
-            self.net.forward(p, [self.frames[i][0] for i in idx])
+            if noise is not None:
+                noise.normal_(generator=gen)
+            self.net.forward(p, [self.frames[i][0] for i in idx], noise, input_noise)
             want = log_every and (it % log_every == 0 or it == 1)
             loss = self.net.backward(p, [self.frames[i][1] for i in idx], g, want_loss=bool(want),
                                      reg=self.reg)
@@ -227,24 +238,25 @@ def forward_rate(ex, reps=20):
 
 def run(n_coarse=256, factor=4, train_seeds=range(100), held_seeds=range(200, 210),
         per_seed=10, horizon=500, iters=2000, batch=8, lr=1e-3, judge_steps=500,
-        judge_every=50, log=None):
+        judge_every=50, input_noise=0.5, kmin=3, log=None):
     """The full learned-closure experiment: generate, train, judge."""
     import time
     say = log or (lambda msg: None)
     ex = Experiment(n_coarse=n_coarse, factor=factor, batch=batch)
     t0 = time.perf_counter()
     ex.generate(held_seeds, 4, horizon, rng_seed=1)
-    held_frames = ex.frames
+    held_frames = [f for f in ex.frames if f[2] >= kmin]
     ex.frames = []
     seeds = list(train_seeds)
     for i in range(0, len(seeds), 20):
         ex.generate(seeds[i:i + 20], per_seed, horizon, rng_seed=i)
         say(f"closure: frames of {min(i + 20, len(seeds))}/{len(seeds)} training seeds")
+    ex.frames = [f for f in ex.frames if f[2] >= kmin]
     gen_s = time.perf_counter() - t0
     say(f"closure: {len(ex.frames)} training and {len(held_frames)} held-out frames in {gen_s:.1f} s")
     ex.fit_norm()
     t0 = time.perf_counter()
-    hist = ex.train(iters, lr=lr, log_every=max(1, iters // 10))
+    hist = ex.train(iters, lr=lr, log_every=max(1, iters // 10), input_noise=input_noise)
     train_s = time.perf_counter() - t0
     say(f"closure: trained {iters} iterations in {train_s:.1f} s, loss {hist[0][1]:.4g} -> {hist[-1][1]:.4g}")
     l_plain, l_corr, explained = ex.explained(held_frames)
@@ -260,7 +272,8 @@ def run(n_coarse=256, factor=4, train_seeds=range(100), held_seeds=range(200, 21
     return {"coarse": n_coarse, "fine": n_coarse * factor, "omega_c": ex.omega_c,
             "train_seeds": len(list(train_seeds)), "held_out_seeds": len(judged),
             "frames": len(ex.frames), "iters": iters, "batch": batch,
-            "restart": ex.restart, "loss_first": hist[0][1], "loss_last": hist[-1][1],
+            "restart": ex.restart, "kmin": kmin, "input_noise": input_noise,
+            "loss_first": hist[0][1], "loss_last": hist[-1][1],
             "reg": ex.reg, "held_out_frames": len(held_frames),
             "one_step_loss_plain": l_plain, "one_step_loss_closure": l_corr,
             "held_out_explained": explained, "fallback_bound": bound, "gen_s": gen_s,

@@ -110,6 +110,7 @@ __device__ __forceinline__ void project(float (&v)[CREAL], const ClNorm &nm)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, ClNorm nm,
+                                                  const float *__restrict__ noise, float amp,
                                                   u16 *__restrict__ x0)
 {
     const int f = blockIdx.z;
@@ -117,16 +118,20 @@ __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, 
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= nx) return;
     const T *P = static_cast<const T *>(post.p[f]);
+    const size_t node = ((size_t)f * ny + y) * nx + x;
+    float v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        v[c] = 0.f;
+        if (c < CREAL) {
+            v[c] = (float)(P[((size_t)y * CREAL + c) * nx + x] - (T)nm.in_mean[c]) * nm.in_inv[c];
+            if (noise) v[c] += amp * noise[node * CREAL + c];
+        }
+    }
     uint32_t w[CH / 2];
 #pragma unroll
-    for (int c = 0; c < CH; c += 2) {
-        float a = 0.f, b = 0.f;
-        if (c < CREAL) a = (float)(P[((size_t)y * CREAL + c) * nx + x] - (T)nm.in_mean[c]) * nm.in_inv[c];
-        if (c + 1 < CREAL)
-            b = (float)(P[((size_t)y * CREAL + c + 1) * nx + x] - (T)nm.in_mean[c + 1]) * nm.in_inv[c + 1];
-        w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
-    }
-    uint4 *dst = reinterpret_cast<uint4 *>(x0 + (((size_t)f * ny + y) * nx + x) * CH);
+    for (int c = 0; c < CH; c += 2) w[c / 2] = (uint32_t)bf16_bits(v[c]) | ((uint32_t)bf16_bits(v[c + 1]) << 16);
+    uint4 *dst = reinterpret_cast<uint4 *>(x0 + node * CH);
 #pragma unroll
     for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
 }
@@ -809,9 +814,10 @@ extern "C" int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, cons
 }
 
 extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const void *const *post,
-                                    int frames, void *stream)
+                                    int frames, const float *noise, float noise_amp, void *stream)
 {
-    if (!c || !params || !post || frames < 1 || frames > c->frames) return PLBM_EINVAL;
+    if (!c || !params || !post || frames < 1 || frames > c->frames || !std::isfinite(noise_amp))
+        return PLBM_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     PtrList pl;
     int rc = make_list(pl, post, frames);
@@ -822,9 +828,11 @@ extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const 
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
     const dim3 gc((c->nx / 32 + 3) / 4, c->ny, frames);
     if (c->f64)
-        hipLaunchKernelGGL(k_cl_input<double>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, c->x0);
+        hipLaunchKernelGGL(k_cl_input<double>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, noise, noise_amp,
+                           c->x0);
     else
-        hipLaunchKernelGGL(k_cl_input<float>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, c->x0);
+        hipLaunchKernelGGL(k_cl_input<float>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, noise, noise_amp,
+                           c->x0);
     // bias of layer l: params + l * LAYER_P + LAYER_W
     hipLaunchKernelGGL(k_cl_conv<0>, gc, dim3(256), 0, st, c->x0, c->wf, params + LAYER_W, nullptr, c->a1,
                        c->nx, c->ny);

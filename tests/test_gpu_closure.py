@@ -95,6 +95,18 @@ def test_input_normalisation(setup):
     assert np.all(x0[..., 25:] == 0)
 
 
+def test_input_noise_is_added_to_the_normalised_input(setup):
+    net = setup["net"]
+    g = torch.Generator(device="cuda").manual_seed(9)
+    noise = torch.randn(FRAMES * N * N * 25, generator=g, device="cuda", dtype=torch.float32)
+    net.forward(setup["params"], setup["posts"], noise, 0.25)
+    x0 = net.activation(0).double().cpu().numpy()
+    X = (setup["P"] - setup["mean"]) / setup["scale"] + 0.25 * noise.double().cpu().numpy().reshape(FRAMES, N, N, 25)
+    assert np.abs(x0[..., :25] - X).max() <= BF * np.abs(X).max() + 1e-6
+    assert np.all(x0[..., 25:] == 0)
+    net.forward(setup["params"], setup["posts"])            # leave the clean activations
+
+
 def test_forward_layers(setup):
     a = setup["acts"]
     (w1, b1), (w2, b2), (w3, b3) = setup["pb"]
