@@ -40,6 +40,10 @@ def _load():
     lib.ref_moments.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, i]
     lib.ref_sums.argtypes = [i, i, i, i, _D, _D, _D]
     lib.ref_num_threads.argtypes = []
+    lib.ref_init3.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D, _D]
+    lib.ref_step3.argtypes = [i, i, i, i, _D, _D, d, _D, i]
+    lib.ref_moments3.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D]
+    lib.ref_sums3.argtypes = [i, i, i, i, _D, _D, _D]
     _lib = lib
     return lib
 
@@ -159,4 +163,60 @@ class Lattice:
                               _p(_f64(f)), _p(out))
         if rc != 0:
             raise ValueError("ref_sums rejected its arguments")
+        return out
+
+
+class Lattice3:
+    """A D3Q125 lattice (tensor product of the 1D rule over three axes,
+    Sec. 2.4) in FP64, periodic.  Populations: float64 arrays of shape
+    (q, nz, ny, nx), k = i + q1d j + q1d^2 l."""
+
+    def __init__(self, nx, ny, nz, v=V_D1Q5, omega=1.0, c=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.v = _f64(v)
+        self.q1d = self.v.size
+        self.q = self.q1d ** 3
+        self.c = lagrange_coeffs(self.v) if c is None else _f64(c)
+        self.omega = float(omega)
+
+    @property
+    def shape(self):
+        return (self.q, self.nz, self.ny, self.nx)
+
+    def init(self, rho, ux, uy, uz, theta):
+        """f(x, 0) = f_eq(rho, u, theta)(x)  (Eq. eqdist, three axes)."""
+        f = np.zeros(self.shape)
+        rc = _load().ref_init3(self.nx, self.ny, self.nz, self.q1d, _p(self.v), _p(self.c),
+                               _p(_f64(rho)), _p(_f64(ux)), _p(_f64(uy)), _p(_f64(uz)),
+                               _p(_f64(theta)), _p(f))
+        if rc != 0:
+            raise ValueError("ref_init3 rejected its arguments")
+        return f
+
+    def step(self, f, nsteps=1):
+        """nsteps applications of Eq. srt (push form); returns a new array."""
+        g = _f64(f).copy()
+        rc = _load().ref_step3(self.nx, self.ny, self.nz, self.q1d, _p(self.v), _p(self.c),
+                               self.omega, _p(g), int(nsteps))
+        if rc != 0:
+            raise ValueError("ref_step3 rejected its arguments")
+        return g
+
+    def moments(self, f):
+        """(rho, ux, uy, uz, theta), each (nz, ny, nx); 3 rho theta = sum f |v - u|^2."""
+        n = self.nx * self.ny * self.nz
+        out = [np.zeros(n) for _ in range(5)]
+        rc = _load().ref_moments3(self.nx, self.ny, self.nz, self.q1d, _p(self.v), _p(_f64(f)),
+                                  *[_p(a) for a in out])
+        if rc != 0:
+            raise ValueError("ref_moments3 rejected its arguments")
+        return tuple(a.reshape(self.nz, self.ny, self.nx) for a in out)
+
+    def sums(self, f):
+        """Compensated (sum f, sum f vx, sum f vy, sum f vz, sum f |v|^2)."""
+        out = np.zeros(5)
+        rc = _load().ref_sums3(self.nx, self.ny, self.nz, self.q1d, _p(self.v), _p(_f64(f)),
+                               _p(out))
+        if rc != 0:
+            raise ValueError("ref_sums3 rejected its arguments")
         return out

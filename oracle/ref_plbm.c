@@ -358,6 +358,160 @@ int ref_sums(int dim, int nx, int ny, int q1d, const double *vel,
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Three dimensions: the tensor product of the 1D rule over three axes  */
+/* (Sec. 2.4: 125 velocities from the five of Eq. 1d5v), periodic.       */
+/* Population k = i + q1d j + q1d^2 l moves with (v_i, v_j, v_l).       */
+/* Layout f[k * nz * ny * nx + (z * ny + y) * nx + x].                   */
+/* ------------------------------------------------------------------ */
+
+#define REF_MAXQ3 (REF_MAXQ * REF_MAXQ * REF_MAXQ)
+
+/* rho, u and theta with 3 rho theta = sum f |v - u|^2 (one temperature). */
+static void node_moments3(int q1d, const double *vel, const double *fk, double *rho,
+                          double *u, double *theta)
+{
+    int q = q1d * q1d * q1d;
+    double s0 = 0.0, s[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < q; ++k) {
+        double v[3] = {vel[k % q1d], vel[(k / q1d) % q1d], vel[k / (q1d * q1d)]};
+        s0 += fk[k];
+        for (int a = 0; a < 3; ++a) s[a] += fk[k] * v[a];
+    }
+    for (int a = 0; a < 3; ++a) u[a] = s[a] / s0;
+    double e = 0.0;
+    for (int k = 0; k < q; ++k) {
+        double v[3] = {vel[k % q1d], vel[(k / q1d) % q1d], vel[k / (q1d * q1d)]};
+        double c2 = 0.0;
+        for (int a = 0; a < 3; ++a) c2 += (v[a] - u[a]) * (v[a] - u[a]);
+        e += fk[k] * c2;
+    }
+    *rho = s0;
+    *theta = e / (3.0 * s0);
+}
+
+/* f_eq_k = rho r_i(u_x, theta) r_j(u_y, theta) r_l(u_z, theta). */
+static void node_equilibrium3(int q1d, const double *c, double rho, const double *u,
+                              double theta, double *feq)
+{
+    double r[3][REF_MAXQ];
+    for (int a = 0; a < 3; ++a) ref_weights_1d(q1d, c, u[a], theta, r[a]);
+    for (int l = 0; l < q1d; ++l)
+        for (int j = 0; j < q1d; ++j)
+            for (int i = 0; i < q1d; ++i)
+                feq[i + q1d * (j + q1d * l)] = rho * r[0][i] * r[1][j] * r[2][l];
+}
+
+static int check_args3(int nx, int ny, int nz, int q1d, const double *vel, int *shift)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || q1d < 1 || q1d > REF_MAXQ) return -1;
+    for (int i = 0; i < q1d; ++i)
+        if (to_shift(vel[i], &shift[i])) return -1;
+    return 0;
+}
+
+int ref_init3(int nx, int ny, int nz, int q1d, const double *vel, const double *c,
+              const double *rho, const double *ux, const double *uy, const double *uz,
+              const double *theta, double *f)
+{
+    int shift[REF_MAXQ];
+    if (check_args3(nx, ny, nz, q1d, vel, shift)) return -1;
+    int q = q1d * q1d * q1d;
+    size_t n = (size_t)nx * ny * nz;
+    double *feq = malloc(sizeof(double) * q);
+    if (!feq) return -1;
+    for (size_t p = 0; p < n; ++p) {
+        double u[3] = {ux[p], uy[p], uz[p]};
+        node_equilibrium3(q1d, c, rho[p], u, theta[p], feq);
+        for (int k = 0; k < q; ++k) f[k * n + p] = feq[k];
+    }
+    free(feq);
+    return 0;
+}
+
+/* nsteps applications of Eq. srt in push form, periodic in x, y and z. */
+int ref_step3(int nx, int ny, int nz, int q1d, const double *vel, const double *c,
+              double omega, double *f, int nsteps)
+{
+    int shift[REF_MAXQ];
+    if (check_args3(nx, ny, nz, q1d, vel, shift)) return -1;
+    int q = q1d * q1d * q1d;
+    size_t n = (size_t)nx * ny * nz;
+    double *post = malloc(sizeof(double) * q * n);
+    if (!post) return -1;
+    for (int step = 0; step < nsteps; ++step) {
+        #pragma omp parallel for schedule(static)
+        for (long long pp = 0; pp < (long long)n; ++pp) {
+            size_t p = (size_t)pp;
+            double fk[REF_MAXQ3], feq[REF_MAXQ3];
+            for (int k = 0; k < q; ++k) fk[k] = f[k * n + p];
+            double rho, u[3], theta;
+            node_moments3(q1d, vel, fk, &rho, u, &theta);
+            node_equilibrium3(q1d, c, rho, u, theta, feq);
+            for (int k = 0; k < q; ++k) post[k * n + p] = (1.0 - omega) * fk[k] + omega * feq[k];
+        }
+        #pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    for (int k = 0; k < q; ++k) {
+                        int xd = ((x + shift[k % q1d]) % nx + nx) % nx;
+                        int yd = ((y + shift[(k / q1d) % q1d]) % ny + ny) % ny;
+                        int zd = ((z + shift[k / (q1d * q1d)]) % nz + nz) % nz;
+                        f[k * n + ((size_t)zd * ny + yd) * nx + xd] =
+                            post[k * n + ((size_t)z * ny + y) * nx + x];
+                    }
+    }
+    free(post);
+    return 0;
+}
+
+int ref_moments3(int nx, int ny, int nz, int q1d, const double *vel, const double *f,
+                 double *rho, double *ux, double *uy, double *uz, double *theta)
+{
+    int shift[REF_MAXQ];
+    if (check_args3(nx, ny, nz, q1d, vel, shift)) return -1;
+    int q = q1d * q1d * q1d;
+    size_t n = (size_t)nx * ny * nz;
+    for (size_t p = 0; p < n; ++p) {
+        double fk[REF_MAXQ3], r, u[3], th;
+        for (int k = 0; k < q; ++k) fk[k] = f[k * n + p];
+        node_moments3(q1d, vel, fk, &r, u, &th);
+        rho[p] = r;
+        ux[p] = u[0];
+        uy[p] = u[1];
+        uz[p] = u[2];
+        theta[p] = th;
+    }
+    return 0;
+}
+
+/* Compensated (sum f, sum f v_x, sum f v_y, sum f v_z, sum f |v|^2). */
+int ref_sums3(int nx, int ny, int nz, int q1d, const double *vel, const double *f, double *out)
+{
+    int shift[REF_MAXQ];
+    if (check_args3(nx, ny, nz, q1d, vel, shift)) return -1;
+    int q = q1d * q1d * q1d;
+    size_t n = (size_t)nx * ny * nz;
+    double s[5] = {0, 0, 0, 0, 0}, comp[5] = {0, 0, 0, 0, 0};
+    for (size_t p = 0; p < n; ++p) {
+        for (int k = 0; k < q; ++k) {
+            double v[3] = {vel[k % q1d], vel[(k / q1d) % q1d], vel[k / (q1d * q1d)]};
+            double g = f[k * n + p];
+            double term[5] = {g, g * v[0], g * v[1], g * v[2],
+                              g * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2])};
+            for (int m = 0; m < 5; ++m) {
+                double t = s[m] + term[m];
+                if (fabs(s[m]) >= fabs(term[m])) comp[m] += (s[m] - t) + term[m];
+                else comp[m] += (term[m] - t) + s[m];
+                s[m] = t;
+            }
+        }
+    }
+    for (int m = 0; m < 5; ++m) out[m] = s[m] + comp[m];
+    return 0;
+}
+
 /* Threads the parallel loops above run on (1 without OpenMP). */
 int ref_num_threads(void)
 {
