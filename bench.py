@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--q9-forms", default="q9f64,q9f32",
                     help="D2Q9 isothermal (zeta = 4) forms timed beside the D2Q25 ones "
                          "(empty: none)")
+    ap.add_argument("--d3-forms", default="f64,f32",
+                    help="storage forms of the D3Q125 Taylor-Green line (empty: skip)")
+    ap.add_argument("--d3-size", type=int, default=256)
+    ap.add_argument("--d3-only", action="store_true",
+                    help="time only the D3Q125 forms and print their line")
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure experiment")
     return ap.parse_args()
@@ -114,6 +119,48 @@ def time_form(storage, n, fields, steps, warmup, theta):
             "gbs": bytes_step / (ms * 1e-3) / 1e9,
             "frac": bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "bytes_per_node": bytes_step // (n * n), "finite_after": finite}
+
+
+def time_form3(storage, n, fields, steps, warmup):
+    """The D3Q125 step (Sec. 2.4) on an n^3 Taylor-Green box, timed like
+    time_form."""
+    import torch
+    from paper_1402_5487_amd.lattice import Lattice3
+    lat = Lattice3(n, n, n, omega=1.6, storage=storage).init(*fields)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bytes_step = lat.bytes_per_step
+    finite = bool(torch.isfinite(lat.moments()[0]).all())
+    del lat
+    torch.cuda.empty_cache()
+    nodes = n ** 3
+    return {"ms_per_step": ms, "mlups": nodes / (ms * 1e-3) / 1e6,
+            "gbs": bytes_step / (ms * 1e-3) / 1e9,
+            "frac": bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_node": bytes_step // nodes, "finite_after": finite}
+
+
+def d3_forms(args):
+    from paper_1402_5487_amd import inputs
+    forms = [f for f in args.d3_forms.split(",") if f]
+    if not forms:
+        return None
+    n = args.d3_size
+    fields = inputs.taylor_green_3d(n, n, n, u0=0.05, theta=1.0 / 3.0)
+    out = {"workload": f"D3Q125 Taylor-Green {n}^3 periodic, u0=0.05, omega=1.6"}
+    steps = max(1, args.steps // 4)
+    for storage in forms:
+        log(f"timing d3q125 {storage} {n}^3 steps={steps} warmup={args.warmup}")
+        out[storage] = time_form3(storage, n, fields, steps, args.warmup)
+    return out
 
 
 def accuracy(forms, n, fields, steps, theta):
@@ -249,6 +296,9 @@ def main():
     if args.closure_only:
         print(json.dumps(closure_form(args)), flush=True)
         return
+    if args.d3_only:
+        print(json.dumps(d3_forms(args)), flush=True)
+        return
 
     n = args.size
     fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80.0, theta=args.theta)
@@ -265,6 +315,8 @@ def main():
     for storage in [f for f in args.q9_forms.split(",") if f]:
         log(f"timing {storage} {n}x{n} steps={args.steps} warmup={args.warmup}")
         d2q9[storage] = time_form(storage, n, fields, args.steps, args.warmup, args.theta)
+
+    d3 = d3_forms(args)
 
     acc = accuracy(forms, n, fields, args.accuracy_steps, args.theta) \
         if args.accuracy_steps > 0 else {}
@@ -322,6 +374,7 @@ def main():
         "vs_fp64_speedup": round(h["mlups"] / results["f64"]["mlups"], 3)
         if "f64" in results else None,
         "d2q9": rnd(d2q9) if d2q9 else None,
+        "d3q125": rnd(d3) if d3 else None,
         "batch": rnd(batch) if batch else None,
         "closure": rnd(closure) if closure else None,
         "copy_gbs": round(copy_gbs, 1),

@@ -32,6 +32,9 @@
  *    in x and y.
  *  - dim 1: element (k, x) at k * (nx + 6) + x + 3: three ghost nodes on each
  *    side of the nx real nodes (zero-gradient ends, see plbm_step).
+ *  - dim 3: element (k, z, y, x) at ((z * ny + y) * q + k) * nx + x with
+ *    q = q1d^3: each lattice row (y, z) stores its q population rows one after
+ *    another.  Periodic in x, y and z.
  *  - element type: double (PLBM_F64), float (PLBM_F32), or 16-bit deviations
  *    (PLBM_F16DEV: IEEE half, PLBM_BF16DEV: bfloat16) decoded as
  *    f_k = rho0 w_k + scale[k] * h_k with w_k = r_i(0, theta0) r_j(0, theta0).
@@ -76,9 +79,12 @@ typedef enum plbm_storage {
 #define PLBM_MAX_Q1D 8
 #define PLBM_GHOST 3          /* largest |velocity| the kernels stream */
 
-/* Plain data describing one lattice.  Copied by value into every launch. */
+/* Plain data describing one lattice.  Copied by value into every launch.
+ * dim 3 is the tensor product of the 1D rule over three axes (Sec. 2.4:
+ * D3Q125 from D1Q5), periodic, FP64 or FP32 storage; population
+ * k = i + q1d j + q1d^2 l moves with (v_i, v_j, v_l). */
 typedef struct plbm_desc {
-    int32_t dim;              /* 1 or 2 */
+    int32_t dim;              /* 1, 2 or 3 */
     int32_t nx, ny;           /* ny = 1 when dim = 1 */
     int32_t q1d;              /* velocities per axis (5 for D1Q5 / D2Q25) */
     int32_t bc;               /* plbm_bc */
@@ -88,6 +94,7 @@ typedef struct plbm_desc {
     double omega;             /* relaxation constant, 0 < omega < 2 */
     double rho0, theta0;      /* deviation base state (16-bit storage only) */
     float scale[PLBM_MAX_Q1D * PLBM_MAX_Q1D]; /* per-plane scale (16-bit) */
+    int32_t nz;               /* dim 3: lattice depth; dims 1 and 2: 1 (0 is read as 1) */
 } plbm_desc;
 
 /*
@@ -108,8 +115,9 @@ int plbm_coeffs(int q, const double *v, double *c);
 
 /*
  * plbm_desc_default -- fill *d for the D1Q5 {0, +-1, +-3} model (dim 1) or its
- * D2Q25 tensor product (dim 2): velocities, c from plbm_coeffs, omega,
- * boundary (periodic in 2D, zero-gradient in 1D), storage, rho0 = 1,
+ * D2Q25 (dim 2) or D3Q125 (dim 3, depth nz = ny; set d->nz for another
+ * depth) tensor product: velocities, c from plbm_coeffs, omega, boundary
+ * (zero-gradient in 1D, periodic otherwise), storage, rho0 = 1,
  * theta0 = 1/3 and unit scales.  Host only.  PLBM_EINVAL on bad sizes.
  */
 int plbm_desc_default(plbm_desc *d, int dim, int nx, int ny, double omega,
@@ -129,10 +137,26 @@ size_t plbm_elem_bytes(const plbm_desc *d);
  *   rho, ux, uy, theta : device pointers to nx*ny doubles (row-major, x
  *                        fastest); uy is ignored (may be NULL) when dim = 1.
  *   f                  : device pointer to plbm_buffer_elems(d) elements.
+ * dim 3 descriptors take plbm_init3 instead (PLBM_EINVAL here).
  * Asynchronous on `stream`.  Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_EHIP.
  */
 int plbm_init(const plbm_desc *d, const double *rho, const double *ux,
               const double *uy, const double *theta, void *f, void *stream);
+
+/*
+ * plbm_init3 -- plbm_init for the D3Q125 model (dim 3, Sec. 2.4: the 1D
+ * rule of Eq. rdr along each of three axes, f_eq_k = rho r_i(u_x) r_j(u_y)
+ * r_l(u_z) for k = i + q1d j + q1d^2 l, one temperature theta).
+ *   rho, ux, uy, uz, theta : device pointers to nx*ny*nz doubles, element
+ *                            (z * ny + y) * nx + x.  All required.
+ *   f                      : device pointer to plbm_buffer_elems(d) elements.
+ * FP64 or FP32 storage, the symmetric five-velocity set.  Asynchronous on
+ * `stream`.  Errors: PLBM_EINVAL (dim != 3, null pointers, bad descriptor),
+ * PLBM_EUNSUPPORTED (16-bit storage or a non-symmetric set), PLBM_EHIP.
+ */
+int plbm_init3(const plbm_desc *d, const double *rho, const double *ux,
+               const double *uy, const double *uz, const double *theta, void *f,
+               void *stream);
 
 /*
  * plbm_step -- nsteps applications of the SRT update, Eq. srt:
@@ -144,15 +168,17 @@ int plbm_init(const plbm_desc *d, const double *rho, const double *ux,
  *              elements.  Step s reads f_a and writes f_b when s is even,
  *              the reverse when odd: the result is in f_a when nsteps is
  *              even and in f_b when it is odd.  nsteps >= 0.
- *   sums     : NULL, or a host pointer to 4 doubles receiving, after the last
- *              step, the FP64 sums over all nodes of the post-collision
- *              populations it wrote: sum f, sum f v_x, sum f v_y,
- *              sum f |v|^2 (mass, momenta, twice the energy).  With periodic
- *              boundaries these are the invariants of the state after the
- *              call.  Asking for sums makes the call synchronise `stream`.
- * Boundaries: dim 2 periodic; dim 1 zero-gradient, i.e. each step the three
- * ghost nodes at each end receive the post-collision populations of the
- * nearest real node before streaming.
+ *   sums     : NULL, or a host pointer to 4 doubles (5 when dim = 3)
+ *              receiving, after the last step, the FP64 sums over all nodes
+ *              of the post-collision populations it wrote: sum f, sum f v_x,
+ *              sum f v_y, sum f |v|^2 (mass, momenta, twice the energy) and,
+ *              in 3D, sum f v_z as the fifth.  With periodic boundaries these
+ *              are the invariants of the state after the call.  Asking for
+ *              sums makes the call synchronise `stream`.
+ * Boundaries: dims 2 and 3 periodic; dim 1 zero-gradient, i.e. each step the
+ * three ghost nodes at each end receive the post-collision populations of
+ * the nearest real node before streaming.  In 3D f_eq = rho r^x r^y r^z and
+ * 3 rho theta = sum f |v - u|^2.
  * Errors: PLBM_EINVAL (aliasing or null buffers, bad descriptor),
  * PLBM_ENONFINITE (sums requested and not finite), PLBM_EHIP.
  */
@@ -172,6 +198,19 @@ int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
  */
 int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
                  double *uy, double *theta, double *sums, void *stream);
+
+/*
+ * plbm_moments3 -- plbm_moments for dim 3: rho, u = (ux, uy, uz) and theta
+ * with 3 rho theta = sum f |v - u|^2 of the pre-collision state held by f.
+ *   rho, ux, uy, uz, theta : device pointers to nx*ny*nz doubles (element
+ *                            (z * ny + y) * nx + x), or NULL to skip a field.
+ *   sums                   : NULL or a host pointer to 5 doubles, in the
+ *                            order of plbm_step's 3D sums.  Asking for sums
+ *                            synchronises `stream`.
+ * Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_ENONFINITE, PLBM_EHIP.
+ */
+int plbm_moments3(const plbm_desc *d, const void *f, double *rho, double *ux,
+                  double *uy, double *uz, double *theta, double *sums, void *stream);
 
 /*
  * plbm_dev_scales -- choose per-plane power-of-two scales for 16-bit

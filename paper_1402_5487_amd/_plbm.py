@@ -48,6 +48,7 @@ class PlbmDesc(ctypes.Structure):
         ("rho0", ctypes.c_double),
         ("theta0", ctypes.c_double),
         ("scale", ctypes.c_float * (MAX_Q1D * MAX_Q1D)),
+        ("nz", ctypes.c_int32),
     ]
 
 
@@ -80,6 +81,8 @@ def _load():
     lib.plbm_step.argtypes = [P, vp, vp, ctypes.c_int, D, vp]
     lib.plbm_moments.argtypes = [P, vp, vp, vp, vp, vp, D, vp]
     lib.plbm_dev_scales.argtypes = [P, vp, vp, vp, vp, vp]
+    lib.plbm_init3.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
+    lib.plbm_moments3.argtypes = [P, vp, vp, vp, vp, vp, vp, D, vp]
     lib.plbm_strerror.argtypes = [ctypes.c_int]
     lib.plbm_strerror.restype = ctypes.c_char_p
     lib.plbm_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -94,7 +97,7 @@ lib = _load()
 EXPORTED = ("plbm_coeffs", "plbm_desc_default", "plbm_buffer_elems",
             "plbm_elem_bytes", "plbm_init", "plbm_step", "plbm_moments",
             "plbm_dev_scales", "plbm_strerror", "plbm_last_hip_error",
-            "plbm_stream_copy")
+            "plbm_stream_copy", "plbm_init3", "plbm_moments3")
 
 
 def strerror(status):
@@ -139,6 +142,16 @@ def desc_q3(dim, nx, ny, omega, storage, zeta=3.0, a=1):
     return d
 
 
+def desc_3d(nx, ny, nz, omega, storage):
+    """Descriptor of the D3Q125 model (dim 3, periodic): the D1Q5 set
+    {0, +-1, +-3} along each axis, depth nz."""
+    d = desc_default(3, nx, ny, omega, storage)
+    d.nz = int(nz)
+    if buffer_elems(d) == 0:
+        raise PlbmError(PLBM_EINVAL, "desc_3d")
+    return d
+
+
 def buffer_elems(d):
     return int(lib.plbm_buffer_elems(ctypes.byref(d)))
 
@@ -161,7 +174,7 @@ def init(d, rho, ux, uy, theta, f, stream):
 
 
 def step(d, fa, fb, nsteps, want_sums, stream):
-    sums = (ctypes.c_double * 4)() if want_sums else None
+    sums = (ctypes.c_double * (5 if d.dim == 3 else 4))() if want_sums else None
     check(lib.plbm_step(ctypes.byref(d), _ptr(fa), _ptr(fb), int(nsteps), sums,
                         _stream(stream)), "plbm_step")
     return list(sums) if want_sums else None
@@ -171,6 +184,18 @@ def moments(d, f, rho, ux, uy, theta, want_sums, stream):
     sums = (ctypes.c_double * 4)() if want_sums else None
     check(lib.plbm_moments(ctypes.byref(d), _ptr(f), _ptr(rho), _ptr(ux), _ptr(uy),
                            _ptr(theta), sums, _stream(stream)), "plbm_moments")
+    return list(sums) if want_sums else None
+
+
+def init3(d, rho, ux, uy, uz, theta, f, stream):
+    check(lib.plbm_init3(ctypes.byref(d), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz), _ptr(theta),
+                         _ptr(f), _stream(stream)), "plbm_init3")
+
+
+def moments3(d, f, rho, ux, uy, uz, theta, want_sums, stream):
+    sums = (ctypes.c_double * 5)() if want_sums else None
+    check(lib.plbm_moments3(ctypes.byref(d), _ptr(f), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz),
+                            _ptr(theta), sums, _stream(stream)), "plbm_moments3")
     return list(sums) if want_sums else None
 
 

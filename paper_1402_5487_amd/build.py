@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplbm.so")
-SOURCES = ["plbm_coeffs.cpp", "plbm_kernels.hip", "plbm_batch.hip", "plbm_closure.hip", "plbm_q3.hip"]
+SOURCES = ["plbm_coeffs.cpp", "plbm_kernels.hip", "plbm_batch.hip", "plbm_closure.hip", "plbm_q3.hip",
+           "plbm_q125.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

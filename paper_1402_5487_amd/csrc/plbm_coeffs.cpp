@@ -76,6 +76,7 @@ extern "C" int plbm_desc_default(plbm_desc *d, int dim, int nx, int ny,
     d->dim = dim;
     d->nx = nx;
     d->ny = dim == 1 ? 1 : ny;
+    d->nz = dim == 3 ? ny : 1;
     d->q1d = 5;
     d->bc = dim == 1 ? PLBM_BC_ZEROGRAD : PLBM_BC_PERIODIC;
     d->storage = storage;
@@ -105,6 +106,7 @@ extern "C" size_t plbm_buffer_elems(const plbm_desc *d)
     if (!d || plbm::validate(d) != PLBM_OK) return 0;
     size_t q = (size_t)plbm::nq(d);
     if (d->dim == 1) return q * (size_t)(d->nx + 2 * PLBM_GHOST);
+    if (d->dim == 3) return q * (size_t)d->nx * (size_t)d->ny * (size_t)d->nz;
     return q * (size_t)d->nx * (size_t)d->ny;
 }
 
@@ -123,19 +125,26 @@ extern "C" const char *plbm_strerror(int status)
 
 namespace plbm {
 
-int nq(const plbm_desc *d) { return d->dim == 1 ? d->q1d : d->q1d * d->q1d; }
+int nq(const plbm_desc *d)
+{
+    return d->dim == 1 ? d->q1d : (d->dim == 2 ? d->q1d * d->q1d : d->q1d * d->q1d * d->q1d);
+}
 
 int validate(const plbm_desc *d)
 {
     if (!d) return PLBM_EINVAL;
-    if (d->dim != 1 && d->dim != 2) return PLBM_EINVAL;
+    if (d->dim < 1 || d->dim > 3) return PLBM_EINVAL;
+    if (d->dim < 3 && d->nz > 1) return PLBM_EINVAL;
+    if (d->dim == 3 && d->nz < 1) return PLBM_EINVAL;
     if (d->q1d < 1 || d->q1d > PLBM_MAX_Q1D) return PLBM_EINVAL;
     if (d->nx < 1 || d->ny < 1) return PLBM_EINVAL;
     if (d->dim == 1 && d->ny != 1) return PLBM_EINVAL;
     if (!(d->omega > 0.0 && d->omega < 2.0)) return PLBM_EINVAL;
     if (d->storage < PLBM_F64 || d->storage > PLBM_BF16DEV) return PLBM_EINVAL;
     if (d->dim == 1 && d->bc != PLBM_BC_ZEROGRAD) return PLBM_EINVAL;
-    if (d->dim == 2 && d->bc != PLBM_BC_PERIODIC) return PLBM_EINVAL;
+    if (d->dim >= 2 && d->bc != PLBM_BC_PERIODIC) return PLBM_EINVAL;
+    // the kernels address a lattice row's population rows with 32-bit byte offsets
+    if (d->dim >= 2 && d->nx > (1 << 26)) return PLBM_EINVAL;
     int maxs = 0;
     for (int i = 0; i < d->q1d; ++i) {
         double r = std::floor(d->v[i] + 0.5);
@@ -150,6 +159,11 @@ int validate(const plbm_desc *d)
         // periodic wrap with one correction needs n >= largest shift
         if (d->nx < maxs || d->ny < maxs) return PLBM_EINVAL;
         if ((double)d->nx * (double)d->ny > (double)(1u << 30)) return PLBM_EINVAL;
+    }
+    if (d->dim == 3) {
+        if (d->nx < maxs || d->ny < maxs || d->nz < maxs) return PLBM_EINVAL;
+        if ((double)d->nx * (double)d->ny * (double)d->nz > (double)(1u << 30)) return PLBM_EINVAL;
+        if (d->storage >= PLBM_F16DEV) return PLBM_EUNSUPPORTED;
     }
     if (d->storage >= PLBM_F16DEV) {
         if (!(d->rho0 > 0.0) || !(d->theta0 > 0.0)) return PLBM_EINVAL;

@@ -191,12 +191,9 @@ __device__ __forceinline__ void sums2d(const typename S::C (&f)[NQ], const KPara
 
 // 1D rule of Eq. rdr for the symmetric set: Maxwell moments of (u, theta)
 // by mu_(n+1) = u mu_n + n theta mu_(n-1), then r = C mu in its reduced form.
-template <class S>
-__device__ __forceinline__ void rule1d(typename S::C u, typename S::C theta, const KParams &p,
-                                       typename S::C (&r)[Q])
+template <typename C>
+__device__ __forceinline__ void rule_sym(C u, C theta, const SymRule<C> &R, C (&r)[Q])
 {
-    using C = typename S::C;
-    const SymRule<C> &R = S::R(p);
     const C m1 = u;
     const C m2 = fma(u, u, theta);
     const C m3 = fma(u, m2, C(2) * theta * u);
@@ -208,6 +205,13 @@ __device__ __forceinline__ void rule1d(typename S::C u, typename S::C theta, con
     r[2] = e1 - o1;
     r[3] = e3 + o3;
     r[4] = e3 - o3;
+}
+
+template <class S>
+__device__ __forceinline__ void rule1d(typename S::C u, typename S::C theta, const KParams &p,
+                                       typename S::C (&r)[Q])
+{
+    rule_sym<typename S::C>(u, theta, S::R(p), r);
 }
 
 // In place: f <- (1 - omega) f + omega f_eq (Eq. srt, collision half), with

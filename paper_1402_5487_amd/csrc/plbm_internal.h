@@ -18,4 +18,7 @@ int q3_init(const plbm_desc *d, const double *rho, const double *ux, const doubl
 int q3_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, void *stream);
 int q3_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy,
                double *theta, double *sums, void *stream);
+
+// The D3Q125 step (plbm_q125.hip); plbm_step forwards dim-3 descriptors here.
+int q125_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, void *stream);
 } // namespace plbm

@@ -68,6 +68,34 @@ def random_fields(nx, ny, seed, theta=(0.34, 0.36), u=0.05, drho=0.02):
     return rho, ux, uy, th
 
 
+def random_fields_3d(nx, ny, nz, seed, theta=(0.34, 0.36), u=0.05, drho=0.02):
+    """random_fields on an (nz, ny, nx) lattice: (rho, ux, uy, uz, theta)."""
+    rng = np.random.default_rng(seed)
+    shp = (nz, ny, nx)
+    rho = 1.0 + drho * rng.uniform(-1, 1, shp)
+    ux, uy, uz = (u * rng.uniform(-1, 1, shp) for _ in range(3))
+    th = rng.uniform(theta[0], theta[1], shp)
+    return rho, ux, uy, uz, th
+
+
+def taylor_green_3d(nx, ny=None, nz=None, u0=0.05, theta=1.0 / 3.0, rho=1.0):
+    """Three-dimensional Taylor-Green vortex on an (nz, ny, nx) periodic box:
+    u = u0 (sin X cos Y cos Z, -cos X sin Y cos Z, 0) with X = 2 pi x / nx
+    etc., uniform density and temperature (the classic decaying-vortex test
+    of three-dimensional solvers)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    X = 2 * np.pi * np.arange(nx) / nx
+    Y = 2 * np.pi * np.arange(ny) / ny
+    Z = 2 * np.pi * np.arange(nz) / nz
+    Zg, Yg, Xg = np.meshgrid(Z, Y, X, indexing="ij")
+    ux = u0 * np.sin(Xg) * np.cos(Yg) * np.cos(Zg)
+    uy = -u0 * np.cos(Xg) * np.sin(Yg) * np.cos(Zg)
+    uz = np.zeros_like(ux)
+    shp = ux.shape
+    return np.full(shp, rho), ux, uy, uz, np.full(shp, theta)
+
+
 @dataclass
 class BatchMember:
     side: int

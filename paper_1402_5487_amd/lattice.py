@@ -113,3 +113,60 @@ class Lattice:
         for k, s in enumerate(st["scale"]):
             self.desc.scale[k] = s
         self.desc.rho0, self.desc.theta0 = st["rho0"], st["theta0"]
+
+
+class Lattice3:
+    """D3Q125 lattice (Sec. 2.4: the D1Q5 rule {0, +-1, +-3} along three
+    axes), periodic, FP64 or FP32 storage.  Fields are (nz, ny, nx) arrays,
+    x fastest."""
+
+    def __init__(self, nx, ny, nz, omega=1.0, storage="f64", device="cuda:0"):
+        self.device = torch.device(device)
+        self.desc = _plbm.desc_3d(nx, ny, nz, omega, storage)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.dtype = _TORCH_DTYPE[self.desc.storage]
+        n = _plbm.buffer_elems(self.desc)
+        self.bufs = [torch.empty(n, dtype=self.dtype, device=self.device),
+                     torch.empty(n, dtype=self.dtype, device=self.device)]
+        self.cur = 0
+        self.t = 0
+
+    @property
+    def stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    @property
+    def f(self):
+        return self.bufs[self.cur]
+
+    @property
+    def bytes_per_step(self):
+        return 2 * 125 * self.nx * self.ny * self.nz * _plbm.elem_bytes(self.desc)
+
+    def init(self, rho, ux, uy, uz, theta):
+        a = [_dev_f64(x, self.device) for x in (rho, ux, uy, uz, theta)]
+        _plbm.init3(self.desc, *a, self.f, self.stream)
+        self.t = 0
+        return self
+
+    def step(self, nsteps=1, sums=False):
+        """nsteps fused steps; with sums, the FP64 (sum f, sum f vx,
+        sum f vy, sum f |v|^2, sum f vz) of the state they leave."""
+        out = _plbm.step(self.desc, self.bufs[self.cur], self.bufs[1 - self.cur], nsteps, sums,
+                         self.stream)
+        if nsteps % 2 == 1:
+            self.cur = 1 - self.cur
+        self.t += nsteps
+        return out
+
+    def moments(self):
+        """(rho, ux, uy, uz, theta) of the current pre-collision state, float64
+        device tensors shaped (nz, ny, nx)."""
+        out = [torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for _ in range(5)]
+        _plbm.moments3(self.desc, self.f, *out, False, self.stream)
+        return tuple(out)
+
+    def sums(self):
+        return _plbm.moments3(self.desc, self.f, None, None, None, None, None, True, self.stream)
+

@@ -42,6 +42,18 @@ def pulled_state(buf, lat):
     return np.stack([a[k, x + 3 - V5[k]] for k in range(5)])
 
 
+def pulled_state3(buf, lat):
+    """D3Q125: pre-collision state (125, nz, ny, nx) of a device buffer laid
+    out as ((z * ny + y) * 125 + k) * nx + x, k = i + 5 j + 25 l."""
+    a = buf.detach().to("cpu").double().numpy()
+    a = a.reshape(lat.nz, lat.ny, 125, lat.nx).transpose(2, 0, 1, 3)
+    out = np.empty_like(a)
+    for k in range(125):
+        i, j, l = k % 5, (k // 5) % 5, k // 25
+        out[k] = np.roll(a[k], (V5[l], V5[j], V5[i]), axis=(0, 1, 2))
+    return out
+
+
 def rel_err(a, b, floor=1.0):
     a, b = np.asarray(a), np.asarray(b)
     return float(np.abs(a - b).max() / max(np.abs(b).max(), floor))

@@ -63,7 +63,7 @@ def test_desc_defaults_and_sizes():
 
 
 @pytest.mark.parametrize("dim,nx,ny,omega,storage", [
-    (3, 10, 10, 1.0, "f64"), (2, 0, 10, 1.0, "f64"), (2, 10, 10, 0.0, "f64"),
+    (4, 10, 10, 1.0, "f64"), (0, 10, 10, 1.0, "f64"), (2, 0, 10, 1.0, "f64"), (2, 10, 10, 0.0, "f64"),
     (2, 10, 10, 2.0, "f64"), (2, 2, 10, 1.0, "f64"), (2, 10, 10, 1.0, 7)])
 def test_desc_rejects(dim, nx, ny, omega, storage):
     with pytest.raises(_plbm.PlbmError) as e:
@@ -165,3 +165,39 @@ def test_three_velocity_family_descriptor_and_rejections():
         assert rc == want, (change, rc)
     d1 = _plbm.desc_q3(1, 1000, 1, 0.93, "f64", zeta=4.0)
     assert _plbm.buffer_elems(d1) == 3 * (1000 + 6)
+
+
+def test_d3q125_descriptor_and_rejections():
+    """dim 3 (D3Q125, Sec. 2.4): 125 populations per node, depth nz; 16-bit
+    storage, a depth below the largest shift, a 2D descriptor with a depth,
+    and the 2D entry points are refused before any device work."""
+    d = _plbm.desc_3d(40, 20, 10, 1.5, "f32")
+    assert d.dim == 3 and d.nz == 10 and d.bc == _plbm.PLBM_BC_PERIODIC
+    assert _plbm.buffer_elems(d) == 125 * 40 * 20 * 10 and _plbm.elem_bytes(d) == 4
+    assert _plbm.desc_default(3, 16, 12, 1.0, "f64").nz == 12      # nz defaults to ny
+    with pytest.raises(_plbm.PlbmError) as e:
+        _plbm.desc_3d(40, 20, 10, 1.5, "f16dev")
+    assert e.value.status == _plbm.PLBM_EUNSUPPORTED
+    for nz in (0, 2):
+        with pytest.raises(_plbm.PlbmError):
+            _plbm.desc_3d(40, 20, nz, 1.5, "f64")
+    d2 = _plbm.desc_default(2, 40, 20, 1.5, "f64")
+    d2.nz = 4
+    assert _plbm.buffer_elems(d2) == 0
+    lib, p, q = _plbm.lib, ctypes.c_void_p(16), ctypes.c_void_p(32)
+    d = _plbm.desc_3d(40, 20, 10, 1.5, "f64")
+    assert lib.plbm_init(ctypes.byref(d), p, p, p, p, q, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_moments(ctypes.byref(d), q, None, None, None, None, None,
+                            None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_init3(ctypes.byref(d), p, p, None, p, p, q, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step(ctypes.byref(d), p, p, 1, None, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step(ctypes.byref(d), p, q, -1, None, None) == _plbm.PLBM_EINVAL
+    d2 = _plbm.desc_default(2, 40, 20, 1.5, "f64")
+    assert lib.plbm_init3(ctypes.byref(d2), p, p, p, p, p, q, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_moments3(ctypes.byref(d2), q, None, None, None, None, None, None,
+                             None) == _plbm.PLBM_EINVAL
+    # rows whose population rows could not be addressed with 32-bit offsets
+    d = _plbm.desc_3d(40, 20, 10, 1.5, "f64")
+    d.nx, d.ny, d.nz = (1 << 26) + 1, 3, 3
+    assert _plbm.buffer_elems(d) == 0
+
