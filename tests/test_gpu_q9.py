@@ -136,6 +136,16 @@ def test_d1q3_shock_tube_f64_matches_oracle():
     assert rel_err(got[1], ref[1], 0.5) < 1e-12
 
 
+def test_d1q3_weak_shock_tube_nu_hat_f64_matches_oracle():
+    """The rho_L / rho_R = 1.1 tube with zeta = 4 at the nu_hat-matched omega."""
+    th0 = 0.25
+    w_hat = 1.0 / (0.5 + 0.5 * (2.0 / np.sqrt(3.0)) * (2.0 / 3.0))
+    fields = inputs.shock_tube(1000, rho_l=1.1, theta_l=th0, rho_r=1.0, theta_r=th0)
+    got, ref = _run_1d(1000, 4.0, w_hat, 418, fields)
+    assert rel_err(got[0], ref[0]) < 1e-12
+    assert rel_err(got[1], ref[1], 0.05) < 1e-12
+
+
 @pytest.mark.parametrize("n", [1, 2, 5, 257])
 def test_d1q3_tiny_and_ragged(n):
     rng = np.random.default_rng(n)

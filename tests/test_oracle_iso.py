@@ -171,6 +171,27 @@ def test_d1q3_zeta4_shock_tube_matches_exact_and_paper():
     assert np.abs(np.diff(u)).sum() < 1.02 * 2 * s.u
 
 
+def test_d1q3_weak_shock_tube_nu_and_nu_hat():
+    """Sec. 3.2, rho_L / rho_R = 1.1 (the figures of the weak shock tube and of
+    the viscosity match): at the viscosity-matched omega = 4 sqrt 3 - 6 the
+    zeta = 4 model differs from the LBGK (omega = 1) by about 0.3 % in density
+    and about 0.003 in u / sqrt(theta0); matching instead with
+    nu_hat = nu (zeta - 1) / 2, which accounts for mu_hat_3 = zeta theta0 u,
+    makes the difference much smaller.  Same step counts as the ratio-6 tube
+    (362 LBGK, 418 zeta = 4)."""
+    r3, u3 = _shock_tube_q3(3.0, 1.0, 362, rho_l=1.1)
+    r4, u4 = _shock_tube_q3(4.0, 4 * np.sqrt(3) - 6, 418, rho_l=1.1)
+    # nu_hat of zeta = 4 equal to nu of the LBGK at omega = 1
+    w_hat = 1.0 / (0.5 + 0.5 * (2.0 / np.sqrt(3.0)) * (2.0 / 3.0))
+    r4h, u4h = _shock_tube_q3(4.0, w_hat, 418, rho_l=1.1)
+    d_rho = np.abs((r4 - r3) / r3).max()
+    d_u = np.abs(u4 - u3).max()
+    assert 0.002 < d_rho < 0.004 and 0.002 < d_u < 0.004, (d_rho, d_u)
+    d_rho_h = np.abs((r4h - r3) / r3).max()
+    d_u_h = np.abs(u4h - u3).max()
+    assert d_rho_h < d_rho / 10 and d_u_h < d_u / 10, (d_rho_h, d_u_h)
+
+
 def test_d1q3_lbgk_shock_tube_oscillates():
     """Sec. 3.2: the LBGK model (zeta = 3, omega = 1, 362 iterations, the same
     physical time) gives an oscillating profile for the same shock tube."""
