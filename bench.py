@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--q9-forms", default="q9f64,q9f32",
                     help="D2Q9 isothermal (zeta = 4) forms timed beside the D2Q25 ones "
                          "(empty: none)")
+    ap.add_argument("--gen-forms", default="d2q16:f32,d2q49:f32,d2q49:f64",
+                    help="general velocity sets (model:storage) timed at the KH size (empty: skip)")
+    ap.add_argument("--gen-only", action="store_true",
+                    help="time only the general-set forms and print their line")
     ap.add_argument("--d3-forms", default="f64,f32",
                     help="storage forms of the D3Q125 Taylor-Green line (empty: skip)")
     ap.add_argument("--d3-size", type=int, default=256)
@@ -160,6 +164,55 @@ def d3_forms(args):
     for storage in forms:
         log(f"timing d3q125 {storage} {n}^3 steps={steps} warmup={args.warmup}")
         out[storage] = time_form3(storage, n, fields, steps, args.warmup)
+    return out
+
+
+# general on-lattice sets (Sec. 2.2) run through the general kernels:
+# (velocities, temperature, isothermal)
+GEN_SETS = {"d2q16": ((1, -1, 3, -3), 4.0 / 3.0, True),
+            "d2q49": ((0, 1, -1, 2, -2, 3, -3), 1.0, False)}
+
+
+def time_gen(model, storage, n, steps, warmup):
+    """A general-set lattice on the KH workload at its own temperature, timed
+    like time_form."""
+    import torch
+    from paper_1402_5487_amd import inputs
+    from paper_1402_5487_amd.lattice import Lattice
+    v, th, iso = GEN_SETS[model]
+    lat = Lattice(2, n, n, omega=1.8, storage=storage, velocities=v, theta0=th if iso else None)
+    lat.init(*inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80.0, theta=th))
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bytes_step = lat.bytes_per_step
+    finite = bool(torch.isfinite(lat.moments()[0]).all())
+    del lat
+    torch.cuda.empty_cache()
+    return {"velocities": list(v), "theta": th, "isothermal": iso,
+            "ms_per_step": ms, "mlups": n * n / (ms * 1e-3) / 1e6,
+            "gbs": bytes_step / (ms * 1e-3) / 1e9,
+            "frac": bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_node": bytes_step // (n * n), "finite_after": finite}
+
+
+def gen_forms(args):
+    forms = [f for f in args.gen_forms.split(",") if f]
+    if not forms:
+        return None
+    out = {"workload": f"KH {args.size}x{args.size} periodic, u0=0.1, omega=1.8, "
+                       "each set at its own temperature"}
+    for form in forms:
+        model, storage = form.split(":")
+        log(f"timing general {model} {storage} {args.size}^2 steps={args.steps}")
+        out[form] = time_gen(model, storage, args.size, args.steps, args.warmup)
     return out
 
 
@@ -299,6 +352,9 @@ def main():
     if args.d3_only:
         print(json.dumps(d3_forms(args)), flush=True)
         return
+    if args.gen_only:
+        print(json.dumps(gen_forms(args)), flush=True)
+        return
 
     n = args.size
     fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80.0, theta=args.theta)
@@ -317,6 +373,7 @@ def main():
         d2q9[storage] = time_form(storage, n, fields, args.steps, args.warmup, args.theta)
 
     d3 = d3_forms(args)
+    gen = gen_forms(args)
 
     acc = accuracy(forms, n, fields, args.accuracy_steps, args.theta) \
         if args.accuracy_steps > 0 else {}
@@ -375,6 +432,7 @@ def main():
         if "f64" in results else None,
         "d2q9": rnd(d2q9) if d2q9 else None,
         "d3q125": rnd(d3) if d3 else None,
+        "general_sets": rnd(gen) if gen else None,
         "batch": rnd(batch) if batch else None,
         "closure": rnd(closure) if closure else None,
         "copy_gbs": round(copy_gbs, 1),

@@ -82,7 +82,18 @@ typedef enum plbm_storage {
 /* Plain data describing one lattice.  Copied by value into every launch.
  * dim 3 is the tensor product of the 1D rule over three axes (Sec. 2.4:
  * D3Q125 from D1Q5), periodic, FP64 or FP32 storage; population
- * k = i + q1d j + q1d^2 l moves with (v_i, v_j, v_l). */
+ * k = i + q1d j + q1d^2 l moves with (v_i, v_j, v_l).
+ *
+ * Which model a descriptor selects (dims 1 and 2):
+ *  - q1d 5, v = (0, a, -a, b, -b): the thermal five-velocity model
+ *    (Eq. 1d5v), every storage form;
+ *  - q1d 3, v = (0, a, -a): the isothermal three-velocity family (Eq. 1d3v)
+ *    at theta0, FP64 or FP32;
+ *  - any other set of 3 to 7 distinct integer velocities (asymmetric sets,
+ *    D1Q4, 6 or 7 velocities; Sec. 2.2): the general kernels, FP64 or FP32,
+ *    with c checked against v (sum_n c_in v_k^n = delta_ik).  Up to four
+ *    velocities the model is isothermal at theta0 (mu_n at the fixed
+ *    temperature), from five on thermal (the local temperature). */
 typedef struct plbm_desc {
     int32_t dim;              /* 1, 2 or 3 */
     int32_t nx, ny;           /* ny = 1 when dim = 1 */
@@ -92,7 +103,8 @@ typedef struct plbm_desc {
     double v[PLBM_MAX_Q1D];   /* 1D velocities, integers, |v| <= PLBM_GHOST */
     double c[PLBM_MAX_Q1D * PLBM_MAX_Q1D];  /* c[i*q1d + j], see plbm_coeffs */
     double omega;             /* relaxation constant, 0 < omega < 2 */
-    double rho0, theta0;      /* deviation base state (16-bit storage only) */
+    double rho0, theta0;      /* deviation base state (16-bit storage); theta0
+                                 is also the temperature of the isothermal models */
     float scale[PLBM_MAX_Q1D * PLBM_MAX_Q1D]; /* per-plane scale (16-bit) */
     int32_t nz;               /* dim 3: lattice depth; dims 1 and 2: 1 (0 is read as 1) */
 } plbm_desc;

@@ -142,6 +142,28 @@ def desc_q3(dim, nx, ny, omega, storage, zeta=3.0, a=1):
     return d
 
 
+def desc_general(dim, nx, ny, omega, storage, v, theta0=None):
+    """Descriptor for any on-lattice 1D velocity set v (3 to 7 distinct
+    integers, |v| <= 3; Sec. 2.2), table from plbm_coeffs.  Sets of up to
+    four velocities are isothermal models at theta0 (required), larger sets
+    thermal.  dim 1: zero-gradient ends; dim 2: tensor product, periodic."""
+    q = len(v)
+    if q <= 4 and theta0 is None:
+        raise ValueError("sets of up to four velocities are isothermal: give theta0")
+    d = desc_default(dim, nx, ny, omega, storage)
+    c = coeffs(v)
+    d.q1d = q
+    for i in range(len(d.v)):
+        d.v[i] = float(v[i]) if i < q else 0.0
+    for i in range(len(d.c)):
+        d.c[i] = c[i // q][i % q] if i < q * q else 0.0
+    if theta0 is not None:
+        d.theta0 = float(theta0)
+    if buffer_elems(d) == 0:
+        raise PlbmError(PLBM_EINVAL, "desc_general")
+    return d
+
+
 def desc_3d(nx, ny, nz, omega, storage):
     """Descriptor of the D3Q125 model (dim 3, periodic): the D1Q5 set
     {0, +-1, +-3} along each axis, depth nz."""

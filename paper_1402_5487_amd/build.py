@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libplbm.so")
 SOURCES = ["plbm_coeffs.cpp", "plbm_kernels.hip", "plbm_batch.hip", "plbm_closure.hip", "plbm_q3.hip",
-           "plbm_q125.hip"]
+           "plbm_q125.hip", "plbm_gen.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -19,6 +19,16 @@ int q3_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, 
 int q3_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy,
                double *theta, double *sums, void *stream);
 
+// General on-lattice velocity sets (plbm_gen.hip): every dim-1/2 descriptor
+// with q1d = 3..7 that the symmetric kernels do not take.  The public
+// plbm_init / plbm_step / plbm_moments forward here when gen_handles is true.
+bool gen_handles(const plbm_desc *d);
+int gen_init(const plbm_desc *d, const double *rho, const double *ux, const double *uy,
+             const double *theta, void *f, void *stream);
+int gen_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, void *stream);
+int gen_moments(const plbm_desc *d, const void *f, double *rho, double *ux, double *uy,
+                double *theta, double *sums, void *stream);
+
 // The D3Q125 step (plbm_q125.hip); plbm_step forwards dim-3 descriptors here.
 int q125_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *sums, void *stream);
 } // namespace plbm

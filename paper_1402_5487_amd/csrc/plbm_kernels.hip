@@ -469,6 +469,7 @@ extern "C" int plbm_init(const plbm_desc *d, const double *rho, const double *ux
                          const double *uy, const double *theta, void *f, void *stream)
 {
     if (d && d->dim == 3) return PLBM_EINVAL;
+    if (plbm::gen_handles(d)) return plbm::gen_init(d, rho, ux, uy, theta, f, stream);
     if (d && d->q1d == 3) return plbm::q3_init(d, rho, ux, uy, f, stream);
     KParams p;
     int rc = make_params(d, p);
@@ -481,6 +482,7 @@ extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, d
                          void *stream)
 {
     if (d && d->dim == 3) return plbm::q125_step(d, f_a, f_b, nsteps, sums, stream);
+    if (plbm::gen_handles(d)) return plbm::gen_step(d, f_a, f_b, nsteps, sums, stream);
     if (d && d->q1d == 3) return plbm::q3_step(d, f_a, f_b, nsteps, sums, stream);
     KParams p;
     int rc = make_params(d, p);
@@ -497,6 +499,7 @@ extern "C" int plbm_moments(const plbm_desc *d, const void *f, double *rho, doub
                             double *uy, double *theta, double *sums, void *stream)
 {
     if (d && d->dim == 3) return PLBM_EINVAL;
+    if (plbm::gen_handles(d)) return plbm::gen_moments(d, f, rho, ux, uy, theta, sums, stream);
     if (d && d->q1d == 3)
         return plbm::q3_moments(d, f, rho, ux, uy, theta, sums, stream);
     KParams p;

@@ -21,17 +21,21 @@ def _dev_f64(a, device):
 class Lattice:
     """D1Q5 (dim 1, zero-gradient ends) or D2Q25 (dim 2, periodic) lattice of
     the thermal five-velocity model, or (zeta given) the isothermal D1Q3 /
-    D2Q9 lattice of the three-velocity family with theta0 = 1 / zeta.
+    D2Q9 lattice of the three-velocity family with theta0 = 1 / zeta, or
+    (velocities given) the model of any on-lattice set of 3 to 7 velocities
+    (isothermal at theta0 for up to four, thermal beyond).
 
     storage: "f64", "f32", "f16dev" or "bf16dev" (16-bit deviations from the
     rest state rho0 w_k with per-plane power-of-two scales; D2Q25 only).
     """
 
     def __init__(self, dim, nx, ny=1, omega=1.0, storage="f64", device="cuda:0",
-                 rho0=1.0, theta0=None, zeta=None):
+                 rho0=1.0, theta0=None, zeta=None, velocities=None):
         self.device = torch.device(device)
         if zeta is not None:
             self.desc = _plbm.desc_q3(dim, nx, ny, omega, storage, zeta=zeta)
+        elif velocities is not None:
+            self.desc = _plbm.desc_general(dim, nx, ny, omega, storage, velocities, theta0)
         else:
             self.desc = _plbm.desc_default(dim, nx, ny, omega, storage)
         if theta0 is not None:

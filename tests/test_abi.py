@@ -97,19 +97,30 @@ def test_step_validates_before_launch():
                          None) == _plbm.PLBM_EUNSUPPORTED
 
 
-def test_asymmetric_set_unsupported_on_device():
-    d = _plbm.desc_default(2, 64, 64, 1.5, "f64")
-    # (0, 1, -1, 2, -3): valid table, but not the symmetric structure the
-    # kernels are compiled for
-    v = (0.0, 1.0, -1.0, 2.0, -3.0)
-    c = _plbm.coeffs(v)
-    for i in range(5):
-        d.v[i] = v[i]
-        for j in range(5):
-            d.c[i * 5 + j] = c[i][j]
-    buf = ctypes.c_void_p(0x1000)
-    assert _plbm.lib.plbm_step(ctypes.byref(d), buf, ctypes.c_void_p(0x2000), 1, None,
-                               None) == _plbm.PLBM_EUNSUPPORTED
+def test_general_sets_are_validated_before_launch():
+    """Asymmetric and q1d = 4, 6, 7 sets take the general kernels; what they
+    cannot run is refused on the host: 16-bit storage, a table that is not
+    the Lagrange table of v, an isothermal set without theta0, q1d = 8."""
+    buf, other = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    lib = _plbm.lib
+    d = _plbm.desc_general(2, 64, 64, 1.5, "f64", (0, 1, -1, 2, -3))
+    assert _plbm.buffer_elems(d) == 25 * 64 * 64
+    d.storage = _plbm.PLBM_F16DEV
+    assert lib.plbm_step(ctypes.byref(d), buf, other, 1, None, None) == _plbm.PLBM_EUNSUPPORTED
+    d = _plbm.desc_general(2, 64, 64, 1.5, "f64", (0, 1, -1, 2, -3))
+    d.c[7] += 1e-3                     # no longer the Lagrange table of v
+    assert lib.plbm_step(ctypes.byref(d), buf, other, 1, None, None) == _plbm.PLBM_EINVAL
+    d = _plbm.desc_general(1, 100, 1, 1.0, "f32", (1, -1, 3, -3), theta0=4 / 3)
+    assert _plbm.buffer_elems(d) == 4 * (100 + 6)
+    d.theta0 = 0.0                     # isothermal sets need their theta0
+    assert lib.plbm_step(ctypes.byref(d), buf, other, 1, None, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step(ctypes.byref(d), buf, buf, 1, None, None) == _plbm.PLBM_EINVAL
+    with pytest.raises(ValueError):
+        _plbm.desc_general(2, 64, 64, 1.5, "f64", (1, -1, 3, -3))
+    d = _plbm.desc_general(2, 64, 64, 1.5, "f64", (0, 1, -1, 2, -2, 3, -3))
+    d.q1d = 8                          # eight distinct velocities cannot fit |v| <= 3
+    d.v[7] = 3.0
+    assert lib.plbm_step(ctypes.byref(d), buf, other, 1, None, None) != _plbm.PLBM_OK
 
 
 def test_dev_scales_must_be_powers_of_two_per_class():
@@ -156,12 +167,12 @@ def test_three_velocity_family_descriptor_and_rejections():
         elif change == "dim1":
             e.dim, e.ny, e.bc = 1, 1, 0
         else:
+            # an asymmetric set goes to the general kernels, which check the
+            # table against v: the symmetric table of (0, 1, -1) is refused
             e.v[2] = -2.0
-            c = _plbm.coeffs([0.0, 1.0, -2.0])
-            for i in range(9):
-                e.c[i] = c[i // 3][i % 3]
         rc = _plbm.lib.plbm_step(ctypes.byref(e), buf, other, 1, None, None)
-        want = _plbm.PLBM_EINVAL if change == "dim1" else _plbm.PLBM_EUNSUPPORTED
+        want = {"f16": _plbm.PLBM_EUNSUPPORTED, "dim1": _plbm.PLBM_EINVAL,
+                "asym": _plbm.PLBM_EINVAL}[change]
         assert rc == want, (change, rc)
     d1 = _plbm.desc_q3(1, 1000, 1, 0.93, "f64", zeta=4.0)
     assert _plbm.buffer_elems(d1) == 3 * (1000 + 6)

@@ -16,7 +16,7 @@ SETS = {
     # the asymmetric three-velocity example of Table 3vel, (0, 2, -4) sqrt(theta0),
     # on the lattice with sqrt(theta0) = 1/2
     "q3_asym": ([0, 1, -2], 0.25, True),
-    "q5_asym": ([0, 1, -1, 2, -3], 1.0, False),
+    "q5_asym": ([0, 1, -1, 2, -3], 0.7, False),
     "q6": ([0, 1, -1, 2, -2, 3], 0.5, False),
     "q7": ([0, 1, -1, 2, -2, 3, -3], 1.0, False),
 }
