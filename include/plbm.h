@@ -343,7 +343,8 @@ typedef struct plbm_closure plbm_closure;      /* opaque, owns workspaces */
 /*
  * plbm_closure_create -- workspaces for up to `frames` coarse lattices of
  * the shape of *coarse (dim 2, FP32 or FP64 storage, nx a multiple of 64,
- * whole-node velocities smaller than nx and ny) processed together.
+ * ny at most 65535, whole-node velocities smaller than nx and ny) processed
+ * together.
  * Synchronous.  Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_EHIP.
  */
 int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_closure **out);
@@ -421,7 +422,8 @@ int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, 
  *   d = (cons(T1) - cons(T0)) - (cons(M1) - cons(M0)),
  * computed in FP64 and rounded once.  fields: host array of 16 device FP64
  * pointers, (rho, u_x, u_y, theta) of T0, T1, M0, M1 in that order, each
- * `nodes` long; out: device FP32, four planes of `nodes`.  Asynchronous.
+ * `nodes` long (1 to 2^30); out: device FP32, four planes of `nodes`.
+ * Asynchronous.  Errors: PLBM_EINVAL (null pointers, nodes out of range).
  */
 int plbm_closure_target(const double *const *fields, size_t nodes, float *out, void *stream);
 
@@ -429,7 +431,7 @@ int plbm_closure_target(const double *const *fields, size_t nodes, float *out, v
  * plbm_restrict -- block means over factor x factor fine nodes of rho,
  * rho u and rho (2 theta + |u|^2), returned as coarse (rho, u, theta).
  * All pointers are device FP64 arrays; fine fields fnx x fny (multiples of
- * factor).  Asynchronous.
+ * factor, at most 65535 coarse rows).  Asynchronous.  Errors: PLBM_EINVAL.
  */
 int plbm_restrict(const double *rho, const double *ux, const double *uy, const double *theta,
                   int fnx, int fny, int factor, double *crho, double *cux, double *cuy,

@@ -182,7 +182,7 @@ int build_tiles(plbm_batch *b)
 
 int grid_of(const plbm_batch *b, int ntiles)
 {
-    if (b->grid_mode <= 0) return ntiles;
+    if (b->grid_mode <= 0) return grid_for(ntiles);
     return std::min(ntiles, b->grid_mode * b->cus);
 }
 

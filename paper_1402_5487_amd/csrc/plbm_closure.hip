@@ -719,6 +719,8 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
     const int rc0 = plbm::validate(coarse);
     if (rc0 != PLBM_OK) return rc0;
     if (coarse->nx % WG_SEG != 0 || coarse->nx < WG_SEG) return PLBM_EUNSUPPORTED;
+    // the closure kernels launch one grid row per lattice row
+    if (coarse->ny > 65535) return PLBM_EUNSUPPORTED;
     KParams kp;
     const int rck = make_params(coarse, kp);
     if (rck != PLBM_OK) return rck;
@@ -957,6 +959,7 @@ extern "C" int plbm_restrict(const double *rho, const double *ux, const double *
 {
     if (!rho || !ux || !uy || !theta || !crho || !cux || !cuy || !ctheta) return PLBM_EINVAL;
     if (factor < 1 || fnx < factor || fny < factor || fnx % factor || fny % factor) return PLBM_EINVAL;
+    if (fny / factor > 65535) return PLBM_EINVAL;     // one grid row per coarse row
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetLastError();
     const int cnx = fnx / factor, cny = fny / factor;
@@ -967,7 +970,7 @@ extern "C" int plbm_restrict(const double *rho, const double *ux, const double *
 
 extern "C" int plbm_closure_target(const double *const *fields, size_t nodes, float *out, void *stream)
 {
-    if (!fields || !out || nodes == 0) return PLBM_EINVAL;
+    if (!fields || !out || nodes == 0 || nodes > ((size_t)1 << 30)) return PLBM_EINVAL;
     Fields16 F;
     for (int i = 0; i < 16; ++i) {
         if (!fields[i]) return PLBM_EINVAL;

@@ -145,6 +145,9 @@ int validate(const plbm_desc *d)
     if (d->dim >= 2 && d->bc != PLBM_BC_PERIODIC) return PLBM_EINVAL;
     // the kernels address a lattice row's population rows with 32-bit byte offsets
     if (d->dim >= 2 && d->nx > (1 << 26)) return PLBM_EINVAL;
+    // node counts (and 1D grid sizes) stay within 2^30
+    const double nodes = (double)d->nx * (double)d->ny * (double)(d->dim == 3 ? d->nz : 1);
+    if (nodes > (double)(1u << 30)) return PLBM_EINVAL;
     int maxs = 0;
     for (int i = 0; i < d->q1d; ++i) {
         double r = std::floor(d->v[i] + 0.5);

@@ -301,6 +301,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_partials(const double *_
 }
 
 // ---------------------------------------------------------------------------
+// Launch grids
+// ---------------------------------------------------------------------------
+// A dispatch counts its work-items in 32 bits and gridDim.y is at most 65536,
+// so every lattice kernel runs a one-dimensional grid of at most MAX_GRID
+// workgroups that walks its row segments, tile = y * tiles_x + tx.
+constexpr int MAX_GRID = 1 << 22;
+inline int grid_for(long long tiles) { return (int)std::min<long long>(tiles, MAX_GRID); }
+
+// ---------------------------------------------------------------------------
 // Tile mapping
 // ---------------------------------------------------------------------------
 // Blocks are dispatched round-robin over the XCDs (block b runs on XCD b % 8).
@@ -473,8 +482,9 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
         } else {
             xs = L::load_off(xb, p.sx[i]);
         }
-        lo[i] = (unsigned)(xs + i * nx * (int)sizeof(T));
-        so[i] = (unsigned)((xb + i * nx) * (int)sizeof(T));
+        // unsigned arithmetic: with nx up to 2^26 the FP64 offsets pass 2^31
+        lo[i] = (unsigned)xs + (unsigned)i * (unsigned)nx * (unsigned)sizeof(T);
+        so[i] = ((unsigned)xb + (unsigned)i * (unsigned)nx) * (unsigned)sizeof(T);
         asm volatile("" : "+v"(lo[i]), "+v"(so[i]));
     }
     const bool full = NV == 1 ? (wx + 64 <= nx) : fast;

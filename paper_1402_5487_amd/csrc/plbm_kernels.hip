@@ -86,24 +86,29 @@ __global__ __launch_bounds__(TX) void k_init2d(const double *__restrict__ rho,
                                                const double *__restrict__ th,
                                                typename S::T *__restrict__ dst, KParams p)
 {
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= p.nx) return;
-    const long long n = (long long)y * p.nx + x;    // fields are (ny, nx) row-major
-    double feq[NQ];
-    equilibrium2d(rho[n], ux[n], uy[n], th[n], p, feq);
+    const int segs = (p.nx + TX - 1) / TX;
+    const long long total = (long long)segs * p.ny;
+#pragma unroll 1
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const int y = (int)(t / segs);
+        const int x = (int)(t - (long long)y * segs) * TX + threadIdx.x;
+        if (x >= p.nx) continue;
+        const long long n = (long long)y * p.nx + x;    // fields are (ny, nx) row-major
+        double feq[NQ];
+        equilibrium2d(rho[n], ux[n], uy[n], th[n], p, feq);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-        int yd = y - p.sx[j];
-        yd += (yd < 0) ? p.ny : 0;
-        yd -= (yd >= p.ny) ? p.ny : 0;
+        for (int j = 0; j < Q; ++j) {
+            int yd = y - p.sx[j];
+            yd += (yd < 0) ? p.ny : 0;
+            yd -= (yd >= p.ny) ? p.ny : 0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            int xd = x - p.sx[i];
-            xd += (xd < 0) ? p.nx : 0;
-            xd -= (xd >= p.nx) ? p.nx : 0;
-            const int k = i + Q * j;
-            dst[k * p.pstride + (long long)yd * p.rstride + xd] = S::enc((typename S::C)feq[k], k, p);
+            for (int i = 0; i < Q; ++i) {
+                int xd = x - p.sx[i];
+                xd += (xd < 0) ? p.nx : 0;
+                xd -= (xd >= p.nx) ? p.nx : 0;
+                const int k = i + Q * j;
+                dst[k * p.pstride + (long long)yd * p.rstride + xd] = S::enc((typename S::C)feq[k], k, p);
+            }
         }
     }
 }
@@ -117,10 +122,14 @@ __global__ __launch_bounds__(TX) void k_moments2d(const typename S::T *__restric
                                                   double *__restrict__ uy, double *__restrict__ th,
                                                   double *__restrict__ partials)
 {
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (x < p.nx) {
+    const int segs = (p.nx + TX - 1) / TX;
+    const long long total = (long long)segs * p.ny;
+#pragma unroll 1
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const int y = (int)(t / segs);
+        const int x = (int)(t - (long long)y * segs) * TX + threadIdx.x;
+        if (x >= p.nx) continue;
         double f[NQ];
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
@@ -145,10 +154,9 @@ __global__ __launch_bounds__(TX) void k_moments2d(const typename S::T *__restric
         if (ux) ux[n] = u;
         if (uy) uy[n] = w;
         if (th) th[n] = 0.5 * (e * inv - u * u - w * w);
-        acc[0] = r; acc[1] = jx; acc[2] = jy; acc[3] = e;
+        acc[0] += r; acc[1] += jx; acc[2] += jy; acc[3] += e;
     }
-    if (partials)
-        block_sums_store<4>(acc, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4);
+    if (partials) block_sums_store<4>(acc, partials + (size_t)blockIdx.x * 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -268,17 +276,21 @@ __global__ __launch_bounds__(TX) void k_devmax2d(const double *__restrict__ rho,
                                                  double *__restrict__ partials)
 {
     __shared__ double red[NQ][TX / 64];
-    const int x = blockIdx.x * TX + threadIdx.x;
-    const int y = blockIdx.y;
     double m[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; ++k) m[k] = 0.0;
-    if (x < p.nx) {
+    const int segs = (p.nx + TX - 1) / TX;
+    const long long total = (long long)segs * p.ny;
+#pragma unroll 1
+    for (long long t = blockIdx.x; t < total; t += gridDim.x) {
+        const int y = (int)(t / segs);
+        const int x = (int)(t - (long long)y * segs) * TX + threadIdx.x;
+        if (x >= p.nx) continue;
         const long long n = (long long)y * p.nx + x;
         double feq[NQ];
         equilibrium2d(rho[n], ux[n], uy[n], th[n], p, feq);
 #pragma unroll
-        for (int k = 0; k < NQ; ++k) m[k] = fabs(feq[k] - base[k]);
+        for (int k = 0; k < NQ; ++k) m[k] = fmax(m[k], fabs(feq[k] - base[k]));
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -292,7 +304,7 @@ __global__ __launch_bounds__(TX) void k_devmax2d(const double *__restrict__ rho,
     if (threadIdx.x < NQ) {
         double v = 0.0;
         for (int w = 0; w < TX / 64; ++w) v = fmax(v, red[threadIdx.x][w]);
-        partials[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * NQ + threadIdx.x] = v;
+        partials[(size_t)blockIdx.x * NQ + threadIdx.x] = v;
     }
 }
 
@@ -339,13 +351,13 @@ int launch_step(const KParams &p, const plbm_desc *d, const void *src, void *dst
     using T = typename S::T;
     clear_launch_error();
     if (d->dim == 2) {
-        nblocks = p.ntiles;
+        nblocks = grid_for(p.ntiles);
         const size_t lds = sizeof(T) == 2 ? PLBM_LDS_CAP_16 : PLBM_LDS_CAP_WIDE;
         if (p.nv == 2)
-            hipLaunchKernelGGL((k_step2d<S, 2, SUMS>), dim3(p.ntiles), dim3(TX), lds, st,
+            hipLaunchKernelGGL((k_step2d<S, 2, SUMS>), dim3(nblocks), dim3(TX), lds, st,
                                (const T *)src, (T *)dst, p, partials);
         else
-            hipLaunchKernelGGL((k_step2d<S, 1, SUMS>), dim3(p.ntiles), dim3(TX), lds, st,
+            hipLaunchKernelGGL((k_step2d<S, 1, SUMS>), dim3(nblocks), dim3(TX), lds, st,
                                (const T *)src, (T *)dst, p, partials);
     } else {
         nblocks = (p.nx + TX - 1) / TX;
@@ -365,7 +377,7 @@ int run_steps(const KParams &p, const plbm_desc *d, void *fa, void *fb, int nste
         void *dst = (s & 1) ? fa : fb;
         const bool last = (s == nsteps - 1);
         if (last && sums) {
-            const int nblocks = d->dim == 2 ? p.ntiles : (p.nx + TX - 1) / TX;
+            const int nblocks = d->dim == 2 ? grid_for(p.ntiles) : (p.nx + TX - 1) / TX;
             double *part = nullptr;
             int rc = hip_ok(
                 hipMallocAsync((void **)&part, ((size_t)nblocks + 1) * 4 * sizeof(double), st));
@@ -388,8 +400,8 @@ int launch_init(const KParams &p, const plbm_desc *d, const double *rho, const d
     using T = typename S::T;
     clear_launch_error();
     if (d->dim == 2) {
-        hipLaunchKernelGGL(k_init2d<S>, dim3((p.nx + TX - 1) / TX, p.ny), dim3(TX), 0, st, rho, ux,
-                           uy, th, (T *)f, p);
+        hipLaunchKernelGGL(k_init2d<S>, dim3(grid_for((long long)((p.nx + TX - 1) / TX) * p.ny)),
+                           dim3(TX), 0, st, rho, ux, uy, th, (T *)f, p);
     } else {
         hipLaunchKernelGGL(k_init1d<S>, dim3((p.nx + 2 * PLBM_GHOST + TX - 1) / TX), dim3(TX), 0,
                            st, rho, ux, th, (T *)f, p);
@@ -404,10 +416,9 @@ int launch_moments(const KParams &p, const plbm_desc *d, const void *f, double *
     using T = typename S::T;
     clear_launch_error();
     if (d->dim == 2) {
-        dim3 g((p.nx + TX - 1) / TX, p.ny);
-        nblocks = (int)(g.x * g.y);
-        hipLaunchKernelGGL(k_moments2d<S>, g, dim3(TX), 0, st, (const T *)f, p, rho, ux, uy, th,
-                           partials);
+        nblocks = grid_for((long long)((p.nx + TX - 1) / TX) * p.ny);
+        hipLaunchKernelGGL(k_moments2d<S>, dim3(nblocks), dim3(TX), 0, st, (const T *)f, p, rho,
+                           ux, uy, th, partials);
     } else {
         nblocks = (p.nx + TX - 1) / TX;
         hipLaunchKernelGGL(k_moments1d<S>, dim3(nblocks), dim3(TX), 0, st, (const T *)f, p, rho, ux,
@@ -509,7 +520,8 @@ extern "C" int plbm_moments(const plbm_desc *d, const void *f, double *rho, doub
     hipStream_t st = as_stream(stream);
     int nb = 0;
     if (!sums) return moments_dispatch(p, d, f, rho, ux, uy, theta, nullptr, st, nb);
-    const int nblocks = d->dim == 2 ? ((p.nx + TX - 1) / TX) * p.ny : (p.nx + TX - 1) / TX;
+    const int nblocks = d->dim == 2 ? grid_for((long long)((p.nx + TX - 1) / TX) * p.ny)
+                                    : (p.nx + TX - 1) / TX;
     double *part = nullptr;
     rc = hip_ok(hipMallocAsync((void **)&part, ((size_t)nblocks + 1) * 4 * sizeof(double), st));
     if (rc != PLBM_OK) return rc;
@@ -533,8 +545,8 @@ extern "C" int plbm_dev_scales(plbm_desc *d, const double *rho, const double *ux
     double w[3], base[NQ];
     rest_weights(p.r64, d->theta0, w);
     for (int k = 0; k < NQ; ++k) base[k] = d->rho0 * w[vclass(k % Q)] * w[vclass(k / Q)];
-    dim3 g((p.nx + TX - 1) / TX, p.ny);
-    const size_t nb = (size_t)g.x * g.y;
+    const dim3 g(grid_for((long long)((p.nx + TX - 1) / TX) * p.ny));
+    const size_t nb = g.x;
     double *buf = nullptr;
     const size_t bytes = (NQ + nb * NQ) * sizeof(double);
     rc = hip_ok(hipMallocAsync((void **)&buf, bytes, st));

@@ -113,7 +113,8 @@ __device__ __forceinline__ void gather125(const T *__restrict__ src, const P3 &p
     unsigned lo[Q];
     const int xc = min(xb, nx - 1);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lo[i] = (unsigned)((wrap(xc - p.sx[i], nx) + i * nx) * (int)sizeof(T));
+    for (int i = 0; i < Q; ++i)   // unsigned: the FP64 offsets pass 2^31 for nx near 2^26
+        lo[i] = ((unsigned)wrap(xc - p.sx[i], nx) + (unsigned)i * (unsigned)nx) * (unsigned)sizeof(T);
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
         const int zs = wrap(z - p.sx[l], p.nz);

@@ -184,24 +184,28 @@ template <typename T>
 __global__ __launch_bounds__(TX) void k_init_q9(const double *__restrict__ rho, const double *__restrict__ ux,
                                                 const double *__restrict__ uy, T *__restrict__ dst, Q9Params p)
 {
-    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y;
-    if (x >= p.nx) return;
-    const long long n = (long long)y * p.nx + x;
-    double rx[Q3], ry[Q3];
-    rule3<double>(ux[n], p.r64, rx);
-    rule3<double>(uy[n], p.r64, ry);
     const long long rowelems = (long long)N9 * p.nx;
+#pragma unroll 1
+    for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+        const int y = tile / p.tiles_x;
+        const int x = (tile - y * p.tiles_x) * TX + threadIdx.x;
+        if (x >= p.nx) continue;
+        const long long n = (long long)y * p.nx + x;
+        double rx[Q3], ry[Q3];
+        rule3<double>(ux[n], p.r64, rx);
+        rule3<double>(uy[n], p.r64, ry);
 #pragma unroll
-    for (int j = 0; j < Q3; ++j) {
-        int yd = y - p.sx[j];
-        yd += (yd < 0) ? p.ny : 0;
-        yd -= (yd >= p.ny) ? p.ny : 0;
+        for (int j = 0; j < Q3; ++j) {
+            int yd = y - p.sx[j];
+            yd += (yd < 0) ? p.ny : 0;
+            yd -= (yd >= p.ny) ? p.ny : 0;
 #pragma unroll
-        for (int i = 0; i < Q3; ++i) {
-            int xd = x - p.sx[i];
-            xd += (xd < 0) ? p.nx : 0;
-            xd -= (xd >= p.nx) ? p.nx : 0;
-            dst[yd * rowelems + (long long)(i + Q3 * j) * p.nx + xd] = (T)(rho[n] * rx[i] * ry[j]);
+            for (int i = 0; i < Q3; ++i) {
+                int xd = x - p.sx[i];
+                xd += (xd < 0) ? p.nx : 0;
+                xd -= (xd >= p.nx) ? p.nx : 0;
+                dst[yd * rowelems + (long long)(i + Q3 * j) * p.nx + xd] = (T)(rho[n] * rx[i] * ry[j]);
+            }
         }
     }
 }
@@ -213,9 +217,12 @@ __global__ __launch_bounds__(TX) void k_moments_q9(const T *__restrict__ src, Q9
                                                    double *__restrict__ ux, double *__restrict__ uy,
                                                    double *__restrict__ th, double *__restrict__ partials)
 {
-    const int x = blockIdx.x * TX + threadIdx.x, y = blockIdx.y;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (x < p.nx) {
+#pragma unroll 1
+    for (int tile = blockIdx.x; tile < p.ntiles; tile += gridDim.x) {
+        const int y = tile / p.tiles_x;
+        const int x = (tile - y * p.tiles_x) * TX + threadIdx.x;
+        if (x >= p.nx) continue;
         double f[N9];
         gather9<T, double>(src, p, x, y, f);
         double r, jx, jy, e;
@@ -226,12 +233,12 @@ __global__ __launch_bounds__(TX) void k_moments_q9(const T *__restrict__ src, Q9
         if (ux) ux[n] = u;
         if (uy) uy[n] = w;
         if (th) th[n] = 0.5 * (e / r - u * u - w * w);
-        acc[0] = r;
-        acc[1] = jx;
-        acc[2] = jy;
-        acc[3] = e;
+        acc[0] += r;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += e;
     }
-    if (partials) block_sums_store<4>(acc, partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4);
+    if (partials) block_sums_store<4>(acc, partials + (size_t)blockIdx.x * 4);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,7 +391,8 @@ void q3_launch(const Q9Params &p, const T *src, T *dst, double *part, hipStream_
 {
     if (p.dim == 2) {
         const size_t lds = sizeof(T) == 8 ? PLBM_Q9_LDS_F64 : PLBM_Q9_LDS_F32;
-        hipLaunchKernelGGL((k_step_q9<T, C, SUMS>), dim3(p.ntiles), dim3(TX), lds, st, src, dst, p, part);
+        hipLaunchKernelGGL((k_step_q9<T, C, SUMS>), dim3(grid_for(p.ntiles)), dim3(TX), lds, st, src, dst, p,
+                           part);
     } else {
         hipLaunchKernelGGL((k_step_q3_1d<T, C, SUMS>), dim3(p.tiles_x), dim3(TX), 0, st, src, dst, p, part);
     }
@@ -393,7 +401,7 @@ void q3_launch(const Q9Params &p, const T *src, T *dst, double *part, hipStream_
 template <typename T, typename C>
 int q9_run(const Q9Params &p, void *fa, void *fb, int nsteps, double *sums, hipStream_t st)
 {
-    const int nblocks = p.dim == 2 ? p.ntiles : p.tiles_x;
+    const int nblocks = p.dim == 2 ? grid_for(p.ntiles) : p.tiles_x;
     for (int s = 0; s < nsteps; ++s) {
         const T *src = static_cast<const T *>((s & 1) ? fb : fa);
         T *dst = static_cast<T *>((s & 1) ? fa : fb);
@@ -435,7 +443,7 @@ int q3_init(const plbm_desc *d, const double *rho, const double *ux, const doubl
             hipLaunchKernelGGL(k_init_q3_1d<float>, g, dim3(TX), 0, st, rho, ux, (float *)f, p);
         return q9_launch_status();
     }
-    const dim3 g((p.nx + TX - 1) / TX, p.ny);
+    const dim3 g(grid_for(p.ntiles));
     if (d->storage == PLBM_F64)
         hipLaunchKernelGGL(k_init_q9<double>, g, dim3(TX), 0, st, rho, ux, uy, (double *)f, p);
     else
@@ -463,8 +471,8 @@ int q3_moments(const plbm_desc *d, const void *f, double *rho, double *ux, doubl
     if (rc != PLBM_OK) return rc;
     if (!f) return PLBM_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const dim3 g((p.nx + TX - 1) / TX, p.ny);
-    const int nblocks = (int)(g.x * g.y);
+    const dim3 g(p.dim == 2 ? grid_for(p.ntiles) : p.tiles_x);
+    const int nblocks = (int)g.x;
     double *part = nullptr;
     if (sums) {
         rc = q9_hip(hipMallocAsync((void **)&part, ((size_t)nblocks + 1) * 4 * sizeof(double), st));

@@ -143,6 +143,19 @@ def test_dev_storage_rejected_in_1d():
                                None) == _plbm.PLBM_EUNSUPPORTED
 
 
+def test_node_count_limit():
+    """Every form keeps its node count within 2^30 (1D included: its grid
+    sizes are computed in 32-bit integers)."""
+    d = _plbm.desc_default(1, 1 << 30, 1, 1.0, "f64")
+    assert _plbm.buffer_elems(d) == 5 * ((1 << 30) + 6)
+    d.nx = (1 << 30) + 1
+    assert _plbm.buffer_elems(d) == 0
+    d = _plbm.desc_default(2, 1 << 15, 1 << 15, 1.0, "f64")
+    assert _plbm.buffer_elems(d) == 25 << 30
+    d.ny += 1
+    assert _plbm.buffer_elems(d) == 0
+
+
 def test_strerror():
     assert _plbm.strerror(0) == "ok"
     assert "non-finite" in _plbm.strerror(_plbm.PLBM_ENONFINITE)
