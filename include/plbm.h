@@ -287,12 +287,14 @@ int plbm_batch_init(plbm_batch *b, int i, const double *rho, const double *ux,
                     const double *uy, const double *theta, void *stream);
 
 /*
- * plbm_batch_autotune -- choose, per size class (max(nx, ny)), the tile
- * shape (width 64/128/256 nodes, 1/2/4/8 passes) and then the grid mode and
- * LDS occupancy cap, by timing launches on this batch.  cache_path (nullable)
- * names a JSON file read first (entries for this architecture are reused
- * without timing) and rewritten with the choices.  Overwrites every
- * population buffer (call before plbm_batch_init).  Synchronises `stream`.
+ * plbm_batch_autotune -- choose the tile shape of every size class
+ * (max(nx, ny); width 64/128/256 nodes, 1/2/4/8 passes) from a few policies
+ * (the narrowest width covering the class, 64-wide, 256-wide; one or two
+ * passes), together with the grid mode and LDS occupancy cap, by timing
+ * whole-batch launches.  cache_path (nullable) names a JSON file read first
+ * (when it holds every class and the grid for this architecture nothing is
+ * timed) and rewritten with the choices.  Overwrites every population
+ * buffer (call before plbm_batch_init).  Synchronises `stream`.
  */
 int plbm_batch_autotune(plbm_batch *b, const char *cache_path, void *stream);
 

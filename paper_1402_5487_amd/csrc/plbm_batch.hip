@@ -15,9 +15,13 @@
 //  * plbm_batch_step replays a captured hipGraph of `graph_steps` consecutive
 //    steps (alternating buffers), so the host issues one graph launch per
 //    graph_steps steps.  No memset is recorded in the graph.
-//  * plbm_batch_autotune times the tile shapes per size class and the grid /
-//    occupancy options on the batch itself and keeps the choice in a small
-//    JSON cache keyed by (architecture, storage, size class).
+//  * Lattices of one size form a shape group: back to back in the pool, one
+//    tile shape, so a tile index decodes arithmetically from a table passed
+//    as a kernel argument (up to 48 sizes; beyond that a work list in device
+//    memory names every tile).
+//  * plbm_batch_autotune times a few tile policies (per-class shapes) with
+//    the grid / occupancy options on the whole batch and keeps the choice in
+//    a small JSON cache keyed by (architecture, storage, size class).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,8 +57,6 @@ struct BTile {
     int shape;          // log2(W / 64) in bits 0..1, R in bits 8..15
 };
 
-constexpr int BATCH_SHAPES_W[3] = {64, 128, 256};
-constexpr int BATCH_R[4] = {1, 2, 4, 8};
 
 __device__ __forceinline__ void batch_tile(const BTile &t, const KParams &proto, int parity)
 {
@@ -69,7 +71,10 @@ __device__ __forceinline__ void batch_tile(const BTile &t, const KParams &proto,
     const int y_first = t.y0 + (w >> lw);
     const int y_step = 4 >> lw;                    // rows per pass
     double acc[4];
-    step_rows<StF32, 1, false>(t.buf[parity], t.buf[parity ^ 1], q, xb, y_first, y_step, R, acc);
+    // select the buffers without indexing t.buf by a runtime value: such an
+    // index makes the compiler place the tile in LDS (10 KB per workgroup)
+    float *const b0 = t.buf[0], *const b1 = t.buf[1];
+    step_rows<StF32, 1, false>(parity ? b1 : b0, parity ? b0 : b1, q, xb, y_first, y_step, R, acc);
 }
 
 __global__ __launch_bounds__(TX) void k_step_batch(const BTile *__restrict__ tiles, int ntiles,
@@ -80,6 +85,59 @@ __global__ __launch_bounds__(TX) void k_step_batch(const BTile *__restrict__ til
     for (int i = slot; i < ntiles; i += gridDim.x) {
         const BTile t = tiles[i];
         batch_tile(t, proto, parity);
+    }
+}
+
+// Shape groups: the lattices of one size (nx, ny) sit back to back in the
+// pool with a uniform stride and share a tile shape, so a tile index decodes
+// arithmetically into (group, lattice, x0, y0) from a table passed as a
+// kernel argument.  A workgroup then starts streaming at once: the only
+// memory read besides the populations is the lattice's relaxation constant,
+// which nothing waits for until the collision.  (A work-list entry read from
+// global memory first costs about half the throughput at 256-node tiles.)
+constexpr int MAX_GROUPS = 48;
+
+struct BGroup {
+    long long base;         // pool element offset of the group's first buffer 0
+    long long stride;       // elements from one lattice's buffer 0 to the next
+    long long half;         // elements from a lattice's buffer 0 to its buffer 1
+    int first_lat;          // position of the group's first lattice in the omega table
+    int tiles_x, tiles_per_lat;
+    int nx, ny;
+    int shape;              // log2(W / 64) in bits 0..1, R in bits 8..15
+};
+
+struct BGroups {
+    int count, ntiles;
+    int first[MAX_GROUPS];  // first tile of each group; INT_MAX past count
+    BGroup g[MAX_GROUPS];
+};
+
+__global__ __launch_bounds__(TX) void k_step_groups(float *__restrict__ pool, const float *__restrict__ omegas,
+                                                    BGroups G, KParams proto, int parity)
+{
+    const int slot = xcd_tile(blockIdx.x, gridDim.x);
+#pragma unroll 1
+    for (int t = slot; t < G.ntiles; t += gridDim.x) {
+        int gi = 0;
+#pragma unroll
+        for (int k = 1; k < MAX_GROUPS; ++k) gi += (t >= G.first[k]) ? 1 : 0;
+        const BGroup &gr = G.g[gi];
+        const int local = t - G.first[gi];
+        const int lat = local / gr.tiles_per_lat;
+        const int lt = local - lat * gr.tiles_per_lat;
+        const int ty = lt / gr.tiles_x, tx = lt - ty * gr.tiles_x;
+        const int lw = gr.shape & 3, R = (gr.shape >> 8) & 0xff;
+        BTile tile;
+        tile.buf[0] = pool + gr.base + (long long)lat * gr.stride;
+        tile.buf[1] = tile.buf[0] + gr.half;
+        tile.nx = gr.nx;
+        tile.ny = gr.ny;
+        tile.omega = omegas[gr.first_lat + lat];
+        tile.x0 = tx * (64 << lw);
+        tile.y0 = ty * ((4 >> lw) * R);
+        tile.shape = gr.shape;
+        batch_tile(tile, proto, parity);
     }
 }
 
@@ -113,8 +171,14 @@ struct plbm_batch {
     KParams kp;                      // kernel parameters shared by all lattices
     std::vector<plbm_lattice_spec> specs;
     std::vector<BLat> lats;          // host copy of the lattice table
-    BTile *d_tiles = nullptr;
+    BTile *d_tiles = nullptr;        // work list (when the sizes exceed MAX_GROUPS)
     int ntiles = 0;
+    // shape groups: lattices of one size, contiguous in the pool
+    bool grouped = false;
+    std::vector<std::vector<int>> group_lats;   // lattice indices per group
+    std::vector<long long> group_base;          // pool offset of each group
+    float *d_omega = nullptr;        // omega per lattice, in group order
+    BGroups groups;
     float *pool = nullptr;
     size_t pool_elems = 0;
     int parity = 0;                  // buffer holding the current state
@@ -153,8 +217,64 @@ BTile make_tile(const BLat &L, int x0, int y0, int shape)
     return t;
 }
 
+ShapeChoice shape_of(const plbm_batch *b, int cls)
+{
+    const auto it = b->shape.find(cls);
+    return it == b->shape.end() ? ShapeChoice{} : it->second;
+}
+
+int shape_bits(const ShapeChoice &sc)
+{
+    const int lw = sc.w == 64 ? 0 : (sc.w == 128 ? 1 : 2);
+    return lw | (sc.r << 8);
+}
+
+// The group table for the groups in `which` (all when empty), each with the
+// tile shape of its size class, or with `force` when given.
+BGroups make_groups(const plbm_batch *b, const std::vector<int> &which, const ShapeChoice *force)
+{
+    BGroups G;
+    std::memset(&G, 0, sizeof(G));
+    int tiles = 0, lat0 = 0, n = 0;
+    for (size_t gi = 0; gi < b->group_lats.size(); ++gi) {
+        const bool take = which.empty() || std::find(which.begin(), which.end(), (int)gi) != which.end();
+        const plbm_lattice_spec &sp = b->specs[b->group_lats[gi][0]];
+        if (take) {
+            const ShapeChoice sc = force ? *force : shape_of(b, size_class(sp));
+            const int h = (256 / sc.w) * sc.r;
+            BGroup &g = G.g[n];
+            g.base = b->group_base[gi];
+            g.half = (long long)padded_elems(sp);
+            g.stride = 2 * g.half;
+            g.first_lat = lat0;
+            g.tiles_x = (sp.nx + sc.w - 1) / sc.w;
+            g.tiles_per_lat = g.tiles_x * ((sp.ny + h - 1) / h);
+            g.nx = sp.nx;
+            g.ny = sp.ny;
+            g.shape = shape_bits(sc);
+            G.first[n] = tiles;
+            tiles += g.tiles_per_lat * (int)b->group_lats[gi].size();
+            ++n;
+        }
+        lat0 += (int)b->group_lats[gi].size();
+    }
+    G.count = n;
+    G.ntiles = tiles;
+    for (int k = n; k < MAX_GROUPS; ++k) G.first[k] = 0x7fffffff;
+    return G;
+}
+
 int build_tiles(plbm_batch *b)
 {
+    if (b->grouped) {
+        b->groups = make_groups(b, {}, nullptr);
+        b->ntiles = b->groups.ntiles;
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        return PLBM_OK;
+    }
     std::vector<BTile> tiles;
     for (size_t i = 0; i < b->specs.size(); ++i) {
         const ShapeChoice sc = b->shape.count(size_class(b->specs[i]))
@@ -192,6 +312,21 @@ int launch_batch(plbm_batch *b, const BTile *tiles, int ntiles, int parity, hipS
     hipLaunchKernelGGL(k_step_batch, dim3(grid_of(b, ntiles)), dim3(TX), b->lds, st, tiles, ntiles,
                        b->kp, parity);
     return hipck(hipGetLastError());
+}
+
+int launch_groups(plbm_batch *b, const BGroups &G, int parity, hipStream_t st)
+{
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_step_groups, dim3(grid_of(b, G.ntiles)), dim3(TX), b->lds, st, b->pool, b->d_omega, G,
+                       b->kp, parity);
+    return hipck(hipGetLastError());
+}
+
+// one step of the whole batch in its current form
+int launch_step(plbm_batch *b, int parity, hipStream_t st)
+{
+    return b->grouped ? launch_groups(b, b->groups, parity, st)
+                      : launch_batch(b, b->d_tiles, b->ntiles, parity, st);
 }
 
 // Cache file: {"entries": [{"arch": "...", "storage": "f32", "class": 64, "w": 128,
@@ -259,8 +394,9 @@ void write_cache(const char *path, const std::map<std::string, ShapeChoice> &all
     std::fclose(fp);
 }
 
-// Median-free timing: best of three runs of `reps` launches.
-int time_launches(plbm_batch *b, const BTile *tiles, int ntiles, int reps, hipStream_t st, float &ms)
+// Median-free timing: best of three runs of `reps` launches of `one(parity)`.
+template <class F>
+int time_runs(F one, int reps, hipStream_t st, float &ms)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return PLBM_EHIP;
@@ -272,7 +408,7 @@ int time_launches(plbm_batch *b, const BTile *tiles, int ntiles, int reps, hipSt
     ms = 1e30f;
     for (int trial = 0; trial < 3 && rc == PLBM_OK; ++trial) {
         rc = hipck(hipEventRecord(e0, st));
-        for (int i = 0; i < reps && rc == PLBM_OK; ++i) rc = launch_batch(b, tiles, ntiles, i & 1, st);
+        for (int i = 0; i < reps && rc == PLBM_OK; ++i) rc = one(i & 1);
         if (rc == PLBM_OK) rc = hipck(hipEventRecord(e1, st));
         if (rc == PLBM_OK) rc = hipck(hipEventSynchronize(e1));
         float t = 0.0f;
@@ -323,18 +459,54 @@ extern "C" int plbm_batch_create(const plbm_desc *proto, const plbm_lattice_spec
         delete b;
         return PLBM_EHIP;
     }
+    // shape groups: lattices of one size, in order of first appearance
+    {
+        std::map<std::pair<int, int>, int> gid;
+        for (int i = 0; i < count; ++i) {
+            const auto key = std::make_pair(specs[i].nx, specs[i].ny);
+            auto it = gid.find(key);
+            if (it == gid.end()) {
+                it = gid.emplace(key, (int)b->group_lats.size()).first;
+                b->group_lats.emplace_back();
+            }
+            b->group_lats[it->second].push_back(i);
+        }
+        b->grouped = (int)b->group_lats.size() <= MAX_GROUPS;
+    }
+    // pool layout: group by group when grouped (uniform stride inside a
+    // group), else in spec order
+    std::vector<int> order;
+    if (b->grouped) {
+        for (const auto &gl : b->group_lats) order.insert(order.end(), gl.begin(), gl.end());
+    } else {
+        for (int i = 0; i < count; ++i) order.push_back(i);
+    }
+    b->lats.assign(count, BLat{});
+    std::vector<size_t> offset(count, 0);
     size_t off = 0;
+    for (int i : order) {
+        offset[i] = off;
+        off += 2 * padded_elems(specs[i]);
+    }
     for (int i = 0; i < count; ++i) {
-        BLat L;
+        BLat &L = b->lats[i];
         const size_t n = padded_elems(specs[i]);
-        L.buf[0] = b->pool + off;
-        L.buf[1] = b->pool + off + n;
-        off += 2 * n;
+        L.buf[0] = b->pool + offset[i];
+        L.buf[1] = b->pool + offset[i] + n;
         L.nx = specs[i].nx;
         L.ny = specs[i].ny;
         L.omega = (float)specs[i].omega;
         L.pad = 0;
-        b->lats.push_back(L);
+    }
+    if (b->grouped) {
+        for (const auto &gl : b->group_lats) b->group_base.push_back((long long)offset[gl[0]]);
+        std::vector<float> om;
+        for (int i : order) om.push_back((float)specs[i].omega);
+        if (hipMalloc((void **)&b->d_omega, om.size() * sizeof(float)) != hipSuccess ||
+            hipMemcpy(b->d_omega, om.data(), om.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            plbm_batch_destroy(b);
+            return PLBM_EHIP;
+        }
     }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -359,6 +531,7 @@ extern "C" int plbm_batch_destroy(plbm_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_omega) (void)hipFree(b->d_omega);
     if (b->pool) (void)hipFree(b->pool);
     delete b;
     return PLBM_OK;
@@ -421,7 +594,7 @@ extern "C" int plbm_batch_step(plbm_batch *b, int nsteps, void *stream)
             rc = hipck(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
             if (rc != PLBM_OK) return rc;
             for (int s = 0; s < b->graph_steps && rc == PLBM_OK; ++s)
-                rc = launch_batch(b, b->d_tiles, b->ntiles, s & 1, b->capture);
+                rc = launch_step(b, s & 1, b->capture);
             const int rc_end = hipck(hipStreamEndCapture(b->capture, &g));
             if (rc == PLBM_OK) rc = rc_end;
             if (rc == PLBM_OK) rc = hipck(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
@@ -430,7 +603,7 @@ extern "C" int plbm_batch_step(plbm_batch *b, int nsteps, void *stream)
         }
         // the recorded graph starts from buffer 0
         if (b->parity != 0) {
-            rc = launch_batch(b, b->d_tiles, b->ntiles, b->parity, st);
+            rc = launch_step(b, b->parity, st);
             if (rc != PLBM_OK) return rc;
             b->parity ^= 1;
             --left;
@@ -442,7 +615,7 @@ extern "C" int plbm_batch_step(plbm_batch *b, int nsteps, void *stream)
         }
     }
     for (; left > 0; --left) {
-        rc = launch_batch(b, b->d_tiles, b->ntiles, b->parity, st);
+        rc = launch_step(b, b->parity, st);
         if (rc != PLBM_OK) return rc;
         b->parity ^= 1;
     }
@@ -471,63 +644,59 @@ extern "C" int plbm_batch_autotune(plbm_batch *b, const char *cache_path, void *
     std::map<int, std::vector<int>> classes;
     for (size_t i = 0; i < b->specs.size(); ++i) classes[size_class(b->specs[i])].push_back((int)i);
 
+    bool cached = have_grid;
+    for (const auto &kv : classes) cached = cached && cache.count(cache_key(arch, kv.first)) > 0;
     int rc = PLBM_OK;
     bool changed = false;
-    for (const auto &kv : classes) {
-        const std::string key = cache_key(arch, kv.first);
-        if (cache.count(key)) {
-            b->shape[kv.first] = cache[key];
-            continue;
-        }
-        float best = 1e30f;
-        ShapeChoice choice;
-        for (int wi = 0; wi < 3; ++wi)
-            for (int ri = 0; ri < 4; ++ri) {
-                const int w = BATCH_SHAPES_W[wi], r = BATCH_R[ri];
-                if (w > 2 * kv.first && w != 64) continue;
-                std::vector<BTile> tl;
-                const int lw = wi, h = (256 / w) * r;
-                for (int li : kv.second)
-                    for (int y0 = 0; y0 < b->specs[li].ny; y0 += h)
-                        for (int x0 = 0; x0 < b->specs[li].nx; x0 += w)
-                            tl.push_back(make_tile(b->lats[li], x0, y0, lw | (r << 8)));
-                BTile *dt = nullptr;
-                rc = hipck(hipMalloc((void **)&dt, tl.size() * sizeof(BTile)));
-                if (rc != PLBM_OK) return rc;
-                rc = hipck(hipMemcpy(dt, tl.data(), tl.size() * sizeof(BTile), hipMemcpyHostToDevice));
-                float ms = 0.0f;
-                if (rc == PLBM_OK) rc = time_launches(b, dt, (int)tl.size(), 10, st, ms);
-                (void)hipFree(dt);
-                if (rc != PLBM_OK) return rc;
-                if (ms < best) {
-                    best = ms;
-                    choice = ShapeChoice{w, r};
-                }
+    if (cached) {
+        for (const auto &kv : classes) b->shape[kv.first] = cache[cache_key(arch, kv.first)];
+        rc = build_tiles(b);
+        if (rc != PLBM_OK) return rc;
+    } else {
+        // Whole-batch timings of a few tile policies x occupancy caps x grid
+        // modes.  (Timing one size class alone is dominated by launch overhead
+        // for the small classes, and one class's shape moves the whole batch
+        // by less than the timing noise, so shapes are chosen as policies.)
+        auto narrow = [](int cls) { return cls <= 64 ? 64 : (cls <= 128 ? 128 : 256); };
+        const int npol = 5;
+        auto policy = [&](int pi, int cls) {
+            switch (pi) {
+            case 0: return ShapeChoice{narrow(cls), 1};
+            case 1: return ShapeChoice{narrow(cls), 2};
+            case 2: return ShapeChoice{64, 1};
+            case 3: return ShapeChoice{64, 2};
+            default: return ShapeChoice{256, 1};
             }
-        b->shape[kv.first] = choice;
-        cache[key] = choice;
-        changed = true;
-    }
-    rc = build_tiles(b);
-    if (rc != PLBM_OK) return rc;
-    if (!have_grid) {
-        // grid and occupancy: one block per tile or k blocks per CU, LDS caps
-        const int modes[4] = {0, 2, 4, 8};
+        };
+        const int modes[3] = {0, 2, 4};
         const int ldss[3] = {0, 40 * 1024, 80 * 1024};
         float best = 1e30f;
-        for (int mi = 0; mi < 4; ++mi)
-            for (int li = 0; li < 3; ++li) {
-                b->grid_mode = modes[mi];
-                b->lds = ldss[li];
-                float ms = 0.0f;
-                rc = time_launches(b, b->d_tiles, b->ntiles, 6, st, ms);
-                if (rc != PLBM_OK) return rc;
-                if (ms < best) {
-                    best = ms;
-                    mode = modes[mi];
-                    lds = ldss[li];
+        int best_pol = 0;
+        for (int pi = 0; pi < npol; ++pi) {
+            for (const auto &kv : classes) b->shape[kv.first] = policy(pi, kv.first);
+            rc = build_tiles(b);
+            if (rc != PLBM_OK) return rc;
+            for (int mi = 0; mi < 3; ++mi)
+                for (int li = 0; li < 3; ++li) {
+                    b->grid_mode = modes[mi];
+                    b->lds = ldss[li];
+                    float ms = 0.0f;
+                    rc = time_runs([&](int par) { return launch_step(b, par, st); }, 4, st, ms);
+                    if (rc != PLBM_OK) return rc;
+                    if (ms < best) {
+                        best = ms;
+                        best_pol = pi;
+                        mode = modes[mi];
+                        lds = ldss[li];
+                    }
                 }
-            }
+        }
+        for (const auto &kv : classes) {
+            b->shape[kv.first] = policy(best_pol, kv.first);
+            cache[cache_key(arch, kv.first)] = b->shape[kv.first];
+        }
+        rc = build_tiles(b);
+        if (rc != PLBM_OK) return rc;
         changed = true;
     }
     b->grid_mode = mode;

@@ -76,6 +76,41 @@ def test_autotuned_batch_is_bitwise_equal_and_cached(reference, tmp_path):
     b2.close()
 
 
+def _bitwise_against_single(specs, steps, tune=None, graph_steps=8):
+    b = Batch(specs)
+    if tune is not None:
+        b.autotune(tune)
+    b.set_graph_steps(graph_steps)
+    for i, (nx, ny, _) in enumerate(specs):
+        b.init(i, *_fields(i % 9, nx, ny))
+    b.step(steps)
+    torch.cuda.synchronize()
+    for i, (nx, ny, om) in enumerate(specs):
+        ref = _single(nx, ny, om, _fields(i % 9, nx, ny), steps)
+        assert torch.equal(b.buffer(i), ref), (i, nx, ny)
+    info = b.info()
+    b.close()
+    return info
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_repeated_sizes_keep_their_own_buffers_and_omega(tuned, tmp_path):
+    """Lattices of one size share a shape group (back to back in the pool,
+    decoded arithmetically); interleaved in the spec list, each still evolves
+    exactly as alone with its own relaxation constant."""
+    specs = [(64, 64, 1.6), (96, 96, 1.7), (64, 64, 1.5), (96, 96, 1.85), (64, 64, 1.9),
+             (7, 5, 1.3), (96, 96, 1.55), (300, 41, 1.75), (7, 5, 1.45)]
+    _bitwise_against_single(specs, 13, tune=(tmp_path / "t.json") if tuned else None)
+
+
+def test_more_sizes_than_groups_use_the_work_list():
+    """More distinct sizes than the group table holds (48): the work-list
+    kernel runs, with the same results."""
+    specs = [(8 + i, 6 + (i % 3), 1.5 + 0.008 * i) for i in range(50)]
+    info = _bitwise_against_single(specs, 11)
+    assert info["tiles"] > 0
+
+
 def test_batch_lattice_matches_oracle():
     steps = 30
     b = _run_batch([steps], 8)
