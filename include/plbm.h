@@ -191,6 +191,8 @@ int plbm_init3(const plbm_desc *d, const double *rho, const double *ux,
  * three ghost nodes at each end receive the post-collision populations of
  * the nearest real node before streaming.  In 3D f_eq = rho r^x r^y r^z and
  * 3 rho theta = sum f |v - u|^2.
+ * Without sums the call only launches kernels on `stream` (no allocation,
+ * copy or synchronisation), so it can be recorded into a HIP graph.
  * Errors: PLBM_EINVAL (aliasing or null buffers, bad descriptor),
  * PLBM_ENONFINITE (sums requested and not finite), PLBM_EHIP.
  */
