@@ -48,7 +48,10 @@ constexpr int TAPS = 9;
 constexpr int LAYER_W = TAPS * CH * CH;
 constexpr int LAYER_P = LAYER_W + CH;          // weights + bias, per layer
 constexpr int NPARAM = 3 * LAYER_P;
-constexpr int WG_ROWS = 16;                    // rows per weight-gradient block
+#ifndef PLBM_WG_ROWS
+#define PLBM_WG_ROWS 16
+#endif
+constexpr int WG_ROWS = PLBM_WG_ROWS;          // rows per weight-gradient block
 constexpr int WG_SEG = 64;                     // nodes per weight-gradient row segment
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -142,124 +145,208 @@ __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, 
 // MODE 1: forward last layer    out = f32(conv + bias)
 // MODE 2: input gradient        out = bf16(conv_mirrored(dz, W^T) * (act > 0))
 // ---------------------------------------------------------------------------
+// A block covers 4 waves x 32 nodes of `rows` consecutive rows; each lane
+// keeps its 18 weight operands in registers across the rows (the weights
+// are the same for every node, and reloading them per row made the L1 read
+// traffic several times the activations').  conv_rows() picks the row count
+// that leaves about 512 blocks (measured best at 8 frames of 256^2, 1.5x
+// faster than one row per block; a single frame keeps one row per block).
+inline int conv_rows(int nx, int ny, int frames)
+{
+    const long long blocks1 = (long long)((nx / 32 + 3) / 4) * ny * frames;
+    return (int)std::max<long long>(1, std::min<long long>(8, blocks1 / 512));
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_cl_conv(const u16 *__restrict__ in, const u16 *__restrict__ wb,
                                                  const float *__restrict__ bias,
                                                  const u16 *__restrict__ act, void *__restrict__ out,
-                                                 int nx, int ny)
+                                                 int nx, int ny, int rows)
 {
-    const int f = blockIdx.z, y = blockIdx.y;
+    const int f = blockIdx.z;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int x0 = (blockIdx.x * 4 + wv) * 32;       // first node of this wave
     if (x0 >= nx) return;
     const int row_i = l & 31, kh = l >> 5;            // A: node row_i, channels 8*kh..
     const size_t fbase = (size_t)f * ny * nx;
-    f32x16 acc = {};
+    // B: column (output channel) l & 31, k = 8*kh.. within each half
+    bf16x8 bw[TAPS][2];
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
-        int dy = t / 3 - 1, dx = t % 3 - 1;
-        if (MODE == 2) {
-            dy = -dy;
-            dx = -dx;
-        }
-        int ys = y + dy;
-        ys += (ys < 0) ? ny : 0;
-        ys -= (ys >= ny) ? ny : 0;
-        int xs = x0 + row_i + dx;
-        xs += (xs < 0) ? nx : 0;
-        xs -= (xs >= nx) ? nx : 0;
-        const u16 *src = in + (fbase + (size_t)ys * nx + xs) * CH;
-        // B: column (output channel) l & 31, k = 8*kh.. within each half
-        const u16 *wt = wb + ((size_t)t * CH + (l & 31)) * CH;
+    for (int t = 0; t < TAPS; ++t)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(src + h * 16 + 8 * kh);
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(wt + h * 16 + 8 * kh);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-        }
-    }
-    // D[i][j]: i = node 8*(r/4) + 4*(l/32) + r%4, j = channel l%32
+        for (int h = 0; h < 2; ++h)
+            bw[t][h] = *reinterpret_cast<const bf16x8 *>(wb + ((size_t)t * CH + (l & 31)) * CH + h * 16 + 8 * kh);
     const int j = l & 31;
     const float bj = (MODE == 2) ? 0.f : bias[j];
+#pragma unroll 1
+    for (int rr = 0; rr < rows; ++rr) {
+        const int y = blockIdx.y * rows + rr;
+        if (y >= ny) break;
+        f32x16 acc = {};
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
-        const size_t node = fbase + (size_t)y * nx + x0 + i;
-        float v = acc[r] + bj;
-        if (MODE == 0) {
-            reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(fmaxf(v, 0.f));
-        } else if (MODE == 1) {
-            reinterpret_cast<float *>(out)[node * CH + j] = v;
-        } else {
-            const float a = bf16_val(act[node * CH + j]);
-            reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(a > 0.f ? v : 0.f);
+        for (int t = 0; t < TAPS; ++t) {
+            int dy = t / 3 - 1, dx = t % 3 - 1;
+            if (MODE == 2) {
+                dy = -dy;
+                dx = -dx;
+            }
+            int ys = y + dy;
+            ys += (ys < 0) ? ny : 0;
+            ys -= (ys >= ny) ? ny : 0;
+            int xs = x0 + row_i + dx;
+            xs += (xs < 0) ? nx : 0;
+            xs -= (xs >= nx) ? nx : 0;
+            const u16 *src = in + (fbase + (size_t)ys * nx + xs) * CH;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(src + h * 16 + 8 * kh);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[t][h], acc, 0, 0, 0);
+            }
+        }
+        // D[i][j]: i = node 8*(r/4) + 4*(l/32) + r%4, j = channel l%32
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
+            const size_t node = fbase + (size_t)y * nx + x0 + i;
+            float v = acc[r] + bj;
+            if (MODE == 0) {
+                reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(fmaxf(v, 0.f));
+            } else if (MODE == 1) {
+                reinterpret_cast<float *>(out)[node * CH + j] = v;
+            } else {
+                const float a = bf16_val(act[node * CH + j]);
+                reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(a > 0.f ? v : 0.f);
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Weight gradient: dW[t][o][i] = sum_p dz[p][o] * a[p + d_t][i], db[o] = sum_p dz[p][o].
-// Block = WG_SEG nodes x WG_ROWS rows of one frame; wave w owns taps w, w+4, w+8.
-// LDS holds dz (channel-major, WG_SEG nodes) and the three input rows around y
-// (channel-major, WG_SEG + 2 nodes each).
+// A 32x32x16 MFMA takes 8 consecutive nodes of one channel per lane, so the
+// node-major activations are transposed through LDS: dz channel-major, and
+// the input rows y-1, y, y+1 channel-major in three copies shifted by
+// dx = -1, 0, +1, so that every operand is one aligned 16-byte LDS read.  The
+// input rows form a ring in LDS, so each row of the block loads one new
+// input row.  Block = WG_SEG nodes x WG_ROWS rows of one frame; wave w owns
+// taps w, w+4, w+8.  The next row's global loads are issued before the
+// current row's MFMAs.
 // ---------------------------------------------------------------------------
+constexpr int WG_LD = WG_SEG + 8;               // LDS row pitch: 144 B, 16-byte aligned
+constexpr int WG_AVEC = (WG_SEG + 2) * CH / 8;  // 16-byte vectors of one input row (66 nodes)
+
+// One input row (nodes x0 - 1 .. x0 + WG_SEG, vectors t and 256 + t of this
+// thread) and one dz row segment (node t/4, channels 8 (t%4) ..).
+struct WgRegs {
+    uint4 dz;
+    uint4 a[2];
+};
+
+__device__ __forceinline__ void wg_load_a(const u16 *__restrict__ a, size_t fbase, int nx, int ny, int x0, int y,
+                                          uint4 (&v)[2])
+{
+    y += (y < 0) ? ny : 0;
+    y -= (y >= ny) ? ny : 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = threadIdx.x + 256 * h;
+        if (i < WG_AVEC) {
+            int xs = x0 + (i >> 2) - 1;
+            xs += (xs < 0) ? nx : 0;
+            xs -= (xs >= nx) ? nx : 0;
+            v[h] = *reinterpret_cast<const uint4 *>(a + (fbase + (size_t)y * nx + xs) * CH + (i & 3) * 8);
+        }
+    }
+}
+
+// input row -> LDS slot, transposed, in the three x shifts
+__device__ __forceinline__ void wg_store_a(u16 (*slot)[CH][WG_LD], const uint4 (&v)[2])
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int i = threadIdx.x + 256 * h;
+        if (i < WG_AVEC) {
+            const int m = i >> 2, c0 = (i & 3) * 8;      // m: node x0 - 1 + m
+            const u16 *e = reinterpret_cast<const u16 *>(&v[h]);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int n = m - dx;                    // copy dx holds node x0 + n + dx - 1
+                if (n >= 0 && n < WG_SEG) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) slot[dx][c0 + k][n] = e[k];
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, const u16 *__restrict__ dz,
                                                   int nx, int ny, float *__restrict__ part)
 {
-    __shared__ u16 sdz[CH][WG_SEG + 8];
-    __shared__ u16 sa[3][CH][WG_SEG + 8];
+    __shared__ __attribute__((aligned(16))) u16 sdz[CH][WG_LD];
+    // a ring of three input rows, each channel-major in three x shifts:
+    // row yy sits in slot (yy - y0 + 1) % 3
+    __shared__ __attribute__((aligned(16))) u16 sa[3][3][CH][WG_LD];
     const int f = blockIdx.z;
     const int segs = nx / WG_SEG;
     const int x0 = (blockIdx.x % segs) * WG_SEG;
     const int y0 = (blockIdx.x / segs) * WG_ROWS;
-    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, t = threadIdx.x;
     const size_t fbase = (size_t)f * ny * nx;
+    const int rows = min(WG_ROWS, ny - y0);
     f32x16 acc[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[q] = f32x16{};
     float bsum = 0.f;
+    {
+        uint4 v[2];
+        wg_load_a(a, fbase, nx, ny, x0, y0 - 1, v);
+        wg_store_a(sa[0], v);
+        wg_load_a(a, fbase, nx, ny, x0, y0, v);
+        wg_store_a(sa[1], v);
+    }
+    WgRegs R;
+    R.dz = *reinterpret_cast<const uint4 *>(dz + (fbase + (size_t)y0 * nx + x0 + (t >> 2)) * CH + (t & 3) * 8);
+    wg_load_a(a, fbase, nx, ny, x0, y0 + 1, R.a);
 
-    for (int r = 0; r < WG_ROWS; ++r) {
+#pragma unroll 1
+    for (int r = 0; r < rows; ++r) {
         const int y = y0 + r;
-        if (y >= ny) break;
-        __syncthreads();
-        // stage dz row: WG_SEG nodes x 32 channels, transposed
-        for (int e = threadIdx.x; e < WG_SEG * CH; e += 256) {
-            const int node = e / CH, c = e % CH;
-            sdz[c][node] = dz[(fbase + (size_t)y * nx + x0 + node) * CH + c];
+        __syncthreads();                 // the previous row's LDS reads are done
+        {
+            const int node = t >> 2, c0 = (t & 3) * 8;
+            const u16 *e = reinterpret_cast<const u16 *>(&R.dz);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sdz[c0 + k][node] = e[k];
         }
-        // stage the three input rows y-1, y, y+1 at x0-1 .. x0+WG_SEG
-        for (int e = threadIdx.x; e < 3 * (WG_SEG + 2) * CH; e += 256) {
-            const int rr = e / ((WG_SEG + 2) * CH);
-            const int rem = e % ((WG_SEG + 2) * CH);
-            const int node = rem / CH, c = rem % CH;
-            int ys = y + rr - 1;
-            ys += (ys < 0) ? ny : 0;
-            ys -= (ys >= ny) ? ny : 0;
-            int xs = x0 + node - 1;
-            xs += (xs < 0) ? nx : 0;
-            xs -= (xs >= nx) ? nx : 0;
-            sa[rr][c][node] = a[(fbase + (size_t)ys * nx + xs) * CH + c];
-        }
+        wg_store_a(sa[(r + 2) % 3], R.a);          // row y + 1
         __syncthreads();
+        if (r + 1 < rows) {
+            R.dz = *reinterpret_cast<const uint4 *>(dz + (fbase + (size_t)(y + 1) * nx + x0 + (t >> 2)) * CH +
+                                                    (t & 3) * 8);
+            wg_load_a(a, fbase, nx, ny, x0, y + 2, R.a);
+        }
         if (wv == 0 && l < CH) {
-            for (int node = 0; node < WG_SEG; ++node) bsum += bf16_val(sdz[l][node]);
+#pragma unroll
+            for (int k = 0; k < WG_SEG; k += 8) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(&sdz[l][k]);
+                const u16 *e = reinterpret_cast<const u16 *>(&q);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) bsum += bf16_val(e[m]);
+            }
         }
         // A = dz^T (row o = l&31, k = nodes), B = a_t (col i = l&31, k = nodes)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const int t = wv + 4 * q;
-            if (t >= TAPS) break;
-            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const int tap = wv + 4 * q;
+            if (tap >= TAPS) break;
+            const int dy = tap / 3, dx = tap % 3;        // input row y + dy - 1
+            const int slot = (r + dy) % 3;
 #pragma unroll
             for (int kc = 0; kc < WG_SEG / 16; ++kc) {
                 const int n0 = kc * 16 + 8 * (l >> 5);
-                bf16x8 av, bv;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    av[e] = __builtin_bit_cast(__bf16, sdz[l & 31][n0 + e]);
-                    bv[e] = __builtin_bit_cast(__bf16, sa[dy + 1][l & 31][n0 + e + dx + 1]);
-                }
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&sdz[l & 31][n0]);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sa[slot][dx][l & 31][n0]);
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[q], 0, 0, 0);
             }
         }
@@ -269,12 +356,12 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
     const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const int t = wv + 4 * q;
-        if (t >= TAPS) break;
+        const int tap = wv + 4 * q;
+        if (tap >= TAPS) break;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int o = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
-            part[blk * LAYER_W + ((size_t)t * CH + o) * CH + (l & 31)] = acc[q][r];
+            part[blk * LAYER_W + ((size_t)tap * CH + o) * CH + (l & 31)] = acc[q][r];
         }
     }
     if (wv == 0 && l < CH) part[nblk * LAYER_W + blk * CH + l] = bsum;
@@ -828,7 +915,8 @@ extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const 
     rc = cast_weights(c, params, st);
     if (rc != PLBM_OK) return rc;
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
-    const dim3 gc((c->nx / 32 + 3) / 4, c->ny, frames);
+    const int crows = conv_rows(c->nx, c->ny, frames);
+    const dim3 gc((c->nx / 32 + 3) / 4, (c->ny + crows - 1) / crows, frames);
     if (c->f64)
         hipLaunchKernelGGL(k_cl_input<double>, gn, dim3(256), 0, st, pl, c->nx, c->ny, c->nm, noise, noise_amp,
                            c->x0);
@@ -837,11 +925,11 @@ extern "C" int plbm_closure_forward(plbm_closure *c, const float *params, const 
                            c->x0);
     // bias of layer l: params + l * LAYER_P + LAYER_W
     hipLaunchKernelGGL(k_cl_conv<0>, gc, dim3(256), 0, st, c->x0, c->wf, params + LAYER_W, nullptr, c->a1,
-                       c->nx, c->ny);
+                       c->nx, c->ny, crows);
     hipLaunchKernelGGL(k_cl_conv<0>, gc, dim3(256), 0, st, c->a1, c->wf + LAYER_W, params + LAYER_P + LAYER_W,
-                       nullptr, c->a2, c->nx, c->ny);
+                       nullptr, c->a2, c->nx, c->ny, crows);
     hipLaunchKernelGGL(k_cl_conv<1>, gc, dim3(256), 0, st, c->a2, c->wf + 2 * LAYER_W,
-                       params + 2 * LAYER_P + LAYER_W, nullptr, c->y3, c->nx, c->ny);
+                       params + 2 * LAYER_P + LAYER_W, nullptr, c->y3, c->nx, c->ny, crows);
     c->frames_in_fwd = frames;
     return ck(hipGetLastError());
 }
@@ -858,7 +946,11 @@ extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const
     if (rc != PLBM_OK) return rc;
     (void)hipGetLastError();
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
-    const dim3 gc((c->nx / 32 + 3) / 4, c->ny, frames);
+    const int crows = conv_rows(c->nx, c->ny, frames);
+    const dim3 gc((c->nx / 32 + 3) / 4, (c->ny + crows - 1) / crows, frames);
+    // the input-gradient pass (with its ReLU mask read) is fastest at half the rows
+    const int brows = std::max(1, crows / 2);
+    const dim3 gb((c->nx / 32 + 3) / 4, (c->ny + brows - 1) / brows, frames);
     const dim3 gw((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS), 1, frames);
     const int nwblk = (int)(gw.x * gw.z);
     const float inv_n = 1.0f / ((float)frames * c->nx * c->ny);
@@ -870,13 +962,13 @@ extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const
     // layer 3: dW3 from a2 and dy3; dz2 = (W3^T dy3) * (a2 > 0)
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a2, c->dy3, c->nx, c->ny, c->part);
     reduce_wgrad(c, nwblk, grads + 2 * LAYER_P, st);
-    hipLaunchKernelGGL(k_cl_conv<2>, gc, dim3(256), 0, st, c->dy3, c->wt + 2 * LAYER_W, nullptr, c->a2,
-                       c->dz2, c->nx, c->ny);
+    hipLaunchKernelGGL(k_cl_conv<2>, gb, dim3(256), 0, st, c->dy3, c->wt + 2 * LAYER_W, nullptr, c->a2,
+                       c->dz2, c->nx, c->ny, brows);
     // layer 2
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a1, c->dz2, c->nx, c->ny, c->part);
     reduce_wgrad(c, nwblk, grads + LAYER_P, st);
-    hipLaunchKernelGGL(k_cl_conv<2>, gc, dim3(256), 0, st, c->dz2, c->wt + LAYER_W, nullptr, c->a1, c->dz1,
-                       c->nx, c->ny);
+    hipLaunchKernelGGL(k_cl_conv<2>, gb, dim3(256), 0, st, c->dz2, c->wt + LAYER_W, nullptr, c->a1, c->dz1,
+                       c->nx, c->ny, brows);
     // layer 1
     hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->x0, c->dz1, c->nx, c->ny, c->part);
     reduce_wgrad(c, nwblk, grads, st);
