@@ -366,7 +366,7 @@ int plbm_closure_set_norm(plbm_closure *c, const float *in_mean, const float *in
  * (post: host array of device pointers, each a population buffer of the
  * coarse lattice in its storage type) with parameters `params` (device,
  * PLBM_CNN_PARAMS floats).  noise: NULL, or device FP32 values added, times
- * noise_amp, to the normalised input, laid out [frame][y][x][k] (training
+ * noise_amp, to the normalised input, laid out [frame][k][y][x] (training
  * augmentation; the caller draws them).  Keeps the activations for
  * plbm_closure_backward and plbm_closure_apply.
  */

@@ -79,8 +79,9 @@ class Closure:
         _plbm.check(_plbm.lib.plbm_closure_set_norm(self.handle, *arr), "plbm_closure_set_norm")
 
     def forward(self, params, posts, noise=None, noise_amp=0.0):
-        """noise: None, or a float32 device tensor of frames * ny * nx * 25
-        values added (times noise_amp) to the normalised input."""
+        """noise: None, or a float32 device tensor of frames * 25 * ny * nx
+        values (planes [frame][k][y][x]) added, times noise_amp, to the
+        normalised input."""
         self._nf = len(posts)
         if noise is not None and (noise.dtype != torch.float32 or
                                   noise.numel() < len(posts) * self.ny * self.nx * 25):

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, 
         v[c] = 0.f;
         if (c < CREAL) {
             v[c] = (float)(P[((size_t)y * CREAL + c) * nx + x] - (T)nm.in_mean[c]) * nm.in_inv[c];
-            if (noise) v[c] += amp * noise[node * CREAL + c];
+            if (noise) v[c] += amp * noise[(((size_t)f * CREAL + c) * ny + y) * nx + x];
         }
     }
     uint32_t w[CH / 2];

@@ -101,7 +101,9 @@ def test_input_noise_is_added_to_the_normalised_input(setup):
     noise = torch.randn(FRAMES * N * N * 25, generator=g, device="cuda", dtype=torch.float32)
     net.forward(setup["params"], setup["posts"], noise, 0.25)
     x0 = net.activation(0).double().cpu().numpy()
-    X = (setup["P"] - setup["mean"]) / setup["scale"] + 0.25 * noise.double().cpu().numpy().reshape(FRAMES, N, N, 25)
+    # noise planes [frame][k][y][x]
+    nz = noise.double().cpu().numpy().reshape(FRAMES, 25, N, N).transpose(0, 2, 3, 1)
+    X = (setup["P"] - setup["mean"]) / setup["scale"] + 0.25 * nz
     assert np.abs(x0[..., :25] - X).max() <= BF * np.abs(X).max() + 1e-6
     assert np.all(x0[..., 25:] == 0)
     net.forward(setup["params"], setup["posts"])            # leave the clean activations
