@@ -230,8 +230,12 @@ int plbm_moments3(const plbm_desc *d, const void *f, double *rho, double *ux,
  * plbm_dev_scales -- choose per-plane power-of-two scales for 16-bit
  * deviation storage from the initial fields: scale[k] = 2^e with e the
  * smallest integer such that max_x |f_eq_k(x) - rho0 w_k| <= 2^e * 2^10
- * (FP16: ample headroom below 65504 and well above the subnormal range).
- * Planes with zero deviation get scale 2^-30.  Writes d->scale.
+ * (FP16: ample headroom below 65504 and well above the subnormal range),
+ * and at least 2^-26 rho0 (rounded down to a power of two), so that the FP32
+ * collision's rounding noise stays a small deviation even for an initial
+ * state at rest.  The scales fit the initial fields: deviations growing
+ * past about 64 times their initial maximum overflow FP16 (reported as
+ * PLBM_ENONFINITE by the sums).  Writes d->scale.
  *   rho, ux, uy, theta : device pointers as for plbm_init.
  * Synchronises `stream`.  Errors: PLBM_EINVAL, PLBM_EHIP.
  */

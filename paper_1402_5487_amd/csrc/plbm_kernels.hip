@@ -570,13 +570,19 @@ extern "C" int plbm_dev_scales(plbm_desc *d, const double *rho, const double *ux
                 if (!std::isfinite(m)) rc = PLBM_ENONFINITE;
                 else cmax[pclass(k)] = std::fmax(cmax[pclass(k)], m);
             }
+        // Floor: the FP32 collision leaves absolute rounding noise of a few
+        // 2^-24 rho0 in any population, which must stay a small deviation
+        // (|h| of order 10) rather than overflow it; an initial state at
+        // rest (deviations of FP64 rounding, ~1e-17) would otherwise get
+        // scales near 1e-20.
+        const int e_floor = (int)std::floor(std::log2(d->rho0)) - 26;
         if (rc == PLBM_OK)
             for (int k = 0; k < NQ; ++k) {
                 // smallest e with max deviation <= 2^e * 2^10 over the class
                 const double m = cmax[pclass(k)];
-                int e = m > 0.0 ? (int)std::ceil(std::log2(m)) - 10 : -30;
+                int e = m > 0.0 ? (int)std::ceil(std::log2(m)) - 10 : e_floor;
                 if (m > 0.0 && std::ldexp(1.0, e + 10) < m) e += 1;
-                d->scale[k] = (float)std::ldexp(1.0, e);
+                d->scale[k] = (float)std::ldexp(1.0, std::max(e, e_floor));
             }
     }
     delete[] host;
