@@ -246,6 +246,23 @@ def test_apply_is_the_oracle_equilibrium_shift(setup):
         assert torch.equal(a, b)
 
 
+def test_non_finite_network_falls_back_to_the_plain_step(setup):
+    """Parameters poisoned with NaN make every correction non-finite: apply
+    skips every node and leaves the post buffers bitwise unchanged, so the
+    run continues as the plain coarse step."""
+    net = setup["net"]
+    bad = setup["params"].clone()
+    bad[::97] = float("nan")
+    posts = [p.clone() for p in setup["posts"]]
+    net.forward(bad, posts)
+    skipped = torch.zeros(1, dtype=torch.int32, device="cuda")
+    net.apply(posts, bound=1e30, skipped=skipped)
+    assert int(skipped.item()) == FRAMES * N * N
+    for a, b in zip(posts, setup["posts"]):
+        assert torch.equal(a, b)
+    net.forward(setup["params"], setup["posts"])            # leave the clean activations
+
+
 def test_fp32_posts_are_read_and_shifted_in_fp32():
     fields = inputs.kelvin_helmholtz(N, N, u0=0.08, delta=3.0, theta=0.35)
     lat = Lattice(2, N, N, omega=1.9, storage="f32").init(*fields)
