@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = [os.path.join(ROOT, "paper_1402_5487_amd", "csrc", n)
               for n in ("plbm_kernels.hip", "plbm_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_kh4096_traffic.json")
-COMPUTE_DTYPE = {"f64": "f64", "f32": "f32", "f16dev": "f32", "bf16dev": "f32"}
+COMPUTE_DTYPE = {"f64": "f64", "f32": "f32", "f16dev": "f32", "bf16dev": "f32",
+                 "f16dev_sr": "f32", "bf16dev_sr": "f32"}
 
 
 def kernel_hash():
@@ -52,7 +53,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--forms", default="f16dev,f64,f32,bf16dev")
+    ap.add_argument("--forms", default="f16dev,f64,f32,bf16dev,f16dev_sr,bf16dev_sr")
     ap.add_argument("--theta", type=float, default=0.35)
     ap.add_argument("--accuracy-steps", type=int, default=5000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -97,6 +98,9 @@ def make_lattice(storage, n, fields, theta):
     from paper_1402_5487_amd.lattice import Lattice
     if storage.startswith("q9"):
         return Lattice(2, n, n, omega=1.8, storage=storage[2:], zeta=4.0).init(*fields)
+    if storage.endswith("_sr"):          # 16-bit deviations, stochastic rounding
+        return Lattice(2, n, n, omega=1.8, storage=storage[:-3], theta0=theta,
+                       rounding="stochastic").init(*fields)
     return Lattice(2, n, n, omega=1.8, storage=storage, theta0=theta).init(*fields)
 
 
@@ -241,6 +245,43 @@ def accuracy(forms, n, fields, steps, theta):
     return out
 
 
+def transport_errors():
+    """Relative errors of the viscosity (decaying shear wave, 128^2, u = 0.01,
+    400 steps) and of the thermal diffusivity (isobaric entropy wave, 128 x 8,
+    1200 steps) against nu = (1/omega - 1/2) theta, per storage form, omega = 1."""
+    import numpy as np
+    from paper_1402_5487_amd import inputs
+    from paper_1402_5487_amd.lattice import Lattice
+
+    def lat(nx, ny, form, th0):
+        st, rnd = (form[:-3], "stochastic") if form.endswith("_sr") else (form, "nearest")
+        return Lattice(2, nx, ny, omega=1.0, storage=st, theta0=th0, rounding=rnd)
+
+    out = {}
+    for form in ("f64", "f32", "f16dev", "bf16dev", "f16dev_sr", "bf16dev_sr"):
+        L, th = 128, 0.35
+        a = lat(L, L, form, th).init(*inputs.shear_wave(L, L, amp=0.01, theta=th))
+        s = np.sin(2 * np.pi * np.arange(L) / L)
+        amp = lambda: (a.moments()[1].cpu().numpy().mean(axis=1) * s).sum() / (s * s).sum()
+        a0 = amp()
+        a.step(400)
+        k = 2 * np.pi / L
+        e_nu = -np.log(amp() / a0) / (k * k * 400) / (0.5 * th) - 1
+        th0, x = 0.5, np.arange(L)
+        tt = np.tile(th0 * (1 + 0.01 * np.sin(2 * np.pi * x / L)), (8, 1))
+        rho = th0 / tt
+        b = lat(L, 8, form, th0).init(rho, 0 * rho, 0 * rho, tt)
+
+        def ent():
+            m = [t.cpu().numpy() for t in b.moments()]
+            return ((m[3].mean(axis=0) - th0) / th0 - (m[0].mean(axis=0) - 1)) @ np.sin(2 * np.pi * x / L)
+        b0 = ent()
+        b.step(1200)
+        e_k = -np.log(ent() / b0) / (k * k * 1200) / (0.5 * th0) - 1
+        out[form] = {"nu_rel_err": float(e_nu), "thermal_diffusivity_rel_err": float(e_k)}
+    return out
+
+
 def copy_bandwidth(reps=20):
     """plbm_stream_copy of 2 GiB: the achievable HBM rate on this machine."""
     import torch
@@ -379,6 +420,7 @@ def main():
         if args.accuracy_steps > 0 else {}
     for k, v in acc.items():
         results[k]["max_abs_err_vs_f64"] = v
+    transport = transport_errors()
     copy_gbs, copy_ok = copy_bandwidth()
     batch = None
     if args.batch_steps > 0:
@@ -428,6 +470,7 @@ def main():
                      "frac": round(h["frac"], 4), "traffic": traffic},
         "cpu_baseline": cpu,
         "forms": rnd(results),
+        "transport": rnd(transport),
         "vs_fp64_speedup": round(h["mlups"] / results["f64"]["mlups"], 3)
         if "f64" in results else None,
         "d2q9": rnd(d2q9) if d2q9 else None,

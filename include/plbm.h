@@ -76,6 +76,19 @@ typedef enum plbm_storage {
     PLBM_BF16DEV = 3
 } plbm_storage;
 
+/* Rounding of the stored 16-bit deviations h = (f - rho0 w) / scale.
+ * NEAREST: round to nearest even.  STOCHASTIC: one of the two neighbouring
+ * 16-bit values, the farther one with probability equal to the distance to
+ * the nearer one in units of their spacing, so the stored value is unbiased;
+ * the random bits hash the node, the population and the value, so results
+ * stay deterministic and independent of how steps are split into calls.
+ * Round to nearest loses every per-step change below half an ulp of the
+ * deviation, which slows or stops slow viscous and thermal decay. */
+typedef enum {
+    PLBM_ROUND_NEAREST = 0,
+    PLBM_ROUND_STOCHASTIC = 1
+} plbm_rounding;
+
 #define PLBM_MAX_Q1D 8
 #define PLBM_GHOST 3          /* largest |velocity| the kernels stream */
 
@@ -107,6 +120,8 @@ typedef struct plbm_desc {
                                  is also the temperature of the isothermal models */
     float scale[PLBM_MAX_Q1D * PLBM_MAX_Q1D]; /* per-plane scale (16-bit) */
     int32_t nz;               /* dim 3: lattice depth; dims 1 and 2: 1 (0 is read as 1) */
+    int32_t rounding;         /* plbm_rounding of the 16-bit deviations (0 for the
+                                 other storage forms) */
 } plbm_desc;
 
 /*

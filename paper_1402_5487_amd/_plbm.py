@@ -27,6 +27,8 @@ PLBM_BC_PERIODIC = 0
 PLBM_BC_ZEROGRAD = 1
 
 PLBM_F64, PLBM_F32, PLBM_F16DEV, PLBM_BF16DEV = 0, 1, 2, 3
+PLBM_ROUND_NEAREST, PLBM_ROUND_STOCHASTIC = 0, 1
+ROUNDING = {"nearest": PLBM_ROUND_NEAREST, "stochastic": PLBM_ROUND_STOCHASTIC}
 STORAGE = {"f64": PLBM_F64, "f32": PLBM_F32, "f16dev": PLBM_F16DEV,
            "bf16dev": PLBM_BF16DEV}
 
@@ -49,6 +51,7 @@ class PlbmDesc(ctypes.Structure):
         ("theta0", ctypes.c_double),
         ("scale", ctypes.c_float * (MAX_Q1D * MAX_Q1D)),
         ("nz", ctypes.c_int32),
+        ("rounding", ctypes.c_int32),
     ]
 
 

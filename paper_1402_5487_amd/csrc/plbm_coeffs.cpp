@@ -141,6 +141,8 @@ int validate(const plbm_desc *d)
     if (d->dim == 1 && d->ny != 1) return PLBM_EINVAL;
     if (!(d->omega > 0.0 && d->omega < 2.0)) return PLBM_EINVAL;
     if (d->storage < PLBM_F64 || d->storage > PLBM_BF16DEV) return PLBM_EINVAL;
+    if (d->rounding != PLBM_ROUND_NEAREST && d->rounding != PLBM_ROUND_STOCHASTIC) return PLBM_EINVAL;
+    if (d->rounding == PLBM_ROUND_STOCHASTIC && d->storage < PLBM_F16DEV) return PLBM_EINVAL;
     if (d->dim == 1 && d->bc != PLBM_BC_ZEROGRAD) return PLBM_EINVAL;
     if (d->dim >= 2 && d->bc != PLBM_BC_PERIODIC) return PLBM_EINVAL;
     // the kernels address a lattice row's population rows with 32-bit byte offsets

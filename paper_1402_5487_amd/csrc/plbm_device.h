@@ -104,7 +104,7 @@ struct StF64 {
     using T = double;
     using C = double;
     static __device__ __forceinline__ C dec(T h, int, const KParams &) { return h; }
-    static __device__ __forceinline__ T enc(C f, int, const KParams &) { return f; }
+    static __device__ __forceinline__ T enc(C f, int, const KParams &, uint32_t = 0) { return f; }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r64; }
 };
 
@@ -112,7 +112,7 @@ struct StF32 {
     using T = float;
     using C = float;
     static __device__ __forceinline__ C dec(T h, int, const KParams &) { return h; }
-    static __device__ __forceinline__ T enc(C f, int, const KParams &) { return f; }
+    static __device__ __forceinline__ T enc(C f, int, const KParams &, uint32_t = 0) { return f; }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r32; }
 };
 
@@ -127,7 +127,7 @@ struct StF16 {
         const int c = pclass(k);
         return fmaf((float)__builtin_bit_cast(_Float16, h), p.dscale[c], p.dbase[c]);
     }
-    static __device__ __forceinline__ T enc(C f, int k, const KParams &p) {
+    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t = 0) {
         const int c = pclass(k);
         return __builtin_bit_cast(uint16_t, (_Float16)fmaf(f, p.dinv[c], p.dnbi[c]));
     }
@@ -141,11 +141,59 @@ struct StBF16 {
         const int c = pclass(k);
         return fmaf(__uint_as_float((uint32_t)h << 16), p.dscale[c], p.dbase[c]);
     }
-    static __device__ __forceinline__ T enc(C f, int k, const KParams &p) {
+    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t = 0) {
         const int c = pclass(k);
         return __builtin_bit_cast(uint16_t, (__bf16)fmaf(f, p.dinv[c], p.dnbi[c]));
     }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r32; }
+};
+
+// Stochastic rounding of the stored deviation: h = (f - base) / scale (exact
+// in FP32, as above) goes to one of its two neighbours in the 16-bit format
+// with probability proportional to its distance from the other, so the
+// stored value is unbiased.  Round to nearest loses every per-step change
+// smaller than half an ulp of the deviation (2^-11 of it in FP16, 2^-8 in
+// BF16): a slowly decaying wave then decays at the wrong rate or not at all.
+// The random bits are a hash of the node, the population and the value's own
+// bits, so results are deterministic and independent of how the steps are
+// split into calls.
+__device__ __forceinline__ uint32_t sr_bits(uint32_t salt, int k, uint32_t vbits)
+{
+    // one multiply per population (the node term is the same for all 25):
+    // integer multiplies issue at a quarter of the vector rate
+    uint32_t h = (salt * 0x85EBCA6Bu ^ (uint32_t)k * 0x632BE5ABu ^ vbits) * 0x9E3779B1u;
+    return h ^ (h >> 16);
+}
+
+// FP16: add 13 random bits below FP16's mantissa to the FP32 magnitude and
+// convert toward zero (one v_cvt_pkrtz).  Exact stochastic rounding in
+// FP16's normal range; below it (|h| < 2^-14, far under the deviations this
+// storage holds) the rounding is biased by less than 2^-25 scale.  |h| past
+// the FP16 range becomes infinity, as with round to nearest, so the sums
+// still report the overflow.
+struct StF16SR : StF16 {
+    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t salt) {
+        const int c = pclass(k);
+        const float v = fmaf(f, p.dinv[c], p.dnbi[c]);
+        const uint32_t vb = __float_as_uint(v);
+        const float vr = __uint_as_float(vb + (sr_bits(salt, k, vb) & 0x1fffu));
+        const uint16_t b = __builtin_bit_cast(uint16_t, __builtin_amdgcn_cvt_pkrtz(vr, 0.0f)[0]);
+        // past the FP16 range (or NaN): infinity of v's sign
+        return fabsf(v) < 65520.f ? b : (uint16_t)(((vb >> 16) & 0x8000u) | 0x7c00u);
+    }
+};
+
+struct StBF16SR : StBF16 {
+    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t salt) {
+        const int c = pclass(k);
+        const float v = fmaf(f, p.dinv[c], p.dnbi[c]);
+        const uint32_t vb = __float_as_uint(v);
+        if ((vb & 0x7f800000u) == 0x7f800000u) return (uint16_t)(vb >> 16);   // inf / NaN
+        // BF16 keeps FP32's upper 16 bits: adding 16 random bits to the
+        // magnitude and truncating rounds up with probability frac(v / ulp)
+        const uint32_t r = sr_bits(salt, k, vb) & 0xffffu;
+        return (uint16_t)((vb + r) >> 16);
+    }
 };
 
 // FP64 arithmetic on FP64 inputs (initialisation, moments, scale search).
@@ -422,13 +470,13 @@ struct Lane<uint16_t, 2> {
 
 template <class S>
 __device__ __forceinline__ void accumulate_sums(const typename S::C (&f)[NQ], const KParams &p,
-                                                double (&acc)[4])
+                                                double (&acc)[4], uint32_t salt)
 {
     // invariants of what is stored (decoded again for the 16-bit forms)
     using C = typename S::C;
     C g[NQ];
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) g[k] = S::dec(S::enc(f[k], k, p), k, p);
+    for (int k = 0; k < NQ; ++k) g[k] = S::dec(S::enc(f[k], k, p, salt), k, p);
     C rho, jx, jy, e;
     sums2d<S>(g, p, rho, jx, jy, e);
     acc[0] += rho;
@@ -533,10 +581,11 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
 #pragma unroll
             for (int k = 0; k < NQ; ++k) f[k] = S::dec(L::get(raw[k], m), k, p);
             collide2d<S>(f, p);
+            const uint32_t salt = (uint32_t)y * (uint32_t)nx + (uint32_t)(xb + m);   // the node
 #pragma unroll
-            for (int k = 0; k < NQ; ++k) out[k][m] = S::enc(f[k], k, p);
+            for (int k = 0; k < NQ; ++k) out[k][m] = S::enc(f[k], k, p, salt);
             if constexpr (SUMS) {
-                if (full || xb + m < nx) accumulate_sums<S>(f, p, acc);
+                if (full || xb + m < nx) accumulate_sums<S>(f, p, acc, salt);
             }
         }
         if (full) {

@@ -107,7 +107,8 @@ __global__ __launch_bounds__(TX) void k_init2d(const double *__restrict__ rho,
                 xd += (xd < 0) ? p.nx : 0;
                 xd -= (xd >= p.nx) ? p.nx : 0;
                 const int k = i + Q * j;
-                dst[k * p.pstride + (long long)yd * p.rstride + xd] = S::enc((typename S::C)feq[k], k, p);
+                dst[k * p.pstride + (long long)yd * p.rstride + xd] =
+                    S::enc((typename S::C)feq[k], k, p, (uint32_t)n);
             }
         }
     }
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(TX) void k_step1d(const typename S::T *__restrict__
         collide1d<S>(f, p);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            const auto h = S::enc(f[k], k, p);
+            const auto h = S::enc(f[k], k, p, (uint32_t)x);
             dst[k * p.pstride + x + PLBM_GHOST] = h;
             // zero-gradient ends: ghosts take the edge node's post-collision value
             if (x == 0)
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(TX) void k_step1d(const typename S::T *__restrict__
         if constexpr (SUMS) {
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                const double g = (double)S::dec(S::enc(f[k], k, p), k, p);
+                const double g = (double)S::dec(S::enc(f[k], k, p, (uint32_t)x), k, p);
                 const double vk = (double)p.sx[k];
                 acc[0] += g; acc[1] += g * vk; acc[3] += g * vk * vk;
             }
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(TX) void k_init1d(const double *__restrict__ rho,
         s = s < 0 ? 0 : (s >= p.nx ? p.nx - 1 : s);   // never pulled; kept finite
         double r[Q];
         rule1d<Fp64Math>(ux[s], th[s], p, r);
-        dst[k * p.pstride + q] = S::enc((typename S::C)(rho[s] * r[k]), k, p);
+        dst[k * p.pstride + q] = S::enc((typename S::C)(rho[s] * r[k]), k, p, (uint32_t)q);
     }
 }
 
@@ -427,31 +428,33 @@ int launch_moments(const KParams &p, const plbm_desc *d, const void *f, double *
     return launch_status();
 }
 
-#define PLBM_DISPATCH(storage, FN, ...)                                                  \
-    switch (storage) {                                                                   \
+#define PLBM_DISPATCH(d, FN, ...)                                                        \
+    switch ((d)->storage + 8 * (d)->rounding) {                                          \
     case PLBM_F64: return FN<StF64>(__VA_ARGS__);                                        \
     case PLBM_F32: return FN<StF32>(__VA_ARGS__);                                        \
     case PLBM_F16DEV: return FN<StF16>(__VA_ARGS__);                                     \
     case PLBM_BF16DEV: return FN<StBF16>(__VA_ARGS__);                                   \
+    case PLBM_F16DEV + 8 * PLBM_ROUND_STOCHASTIC: return FN<StF16SR>(__VA_ARGS__);       \
+    case PLBM_BF16DEV + 8 * PLBM_ROUND_STOCHASTIC: return FN<StBF16SR>(__VA_ARGS__);     \
     default: return PLBM_EINVAL;                                                         \
     }
 
 int init_dispatch(const KParams &p, const plbm_desc *d, const double *rho, const double *ux,
                   const double *uy, const double *th, void *f, hipStream_t st)
 {
-    PLBM_DISPATCH(d->storage, launch_init, p, d, rho, ux, uy, th, f, st);
+    PLBM_DISPATCH(d, launch_init, p, d, rho, ux, uy, th, f, st);
 }
 
 int step_dispatch(const KParams &p, const plbm_desc *d, void *fa, void *fb, int n, double *sums,
                   hipStream_t st)
 {
-    PLBM_DISPATCH(d->storage, run_steps, p, d, fa, fb, n, sums, st);
+    PLBM_DISPATCH(d, run_steps, p, d, fa, fb, n, sums, st);
 }
 
 int moments_dispatch(const KParams &p, const plbm_desc *d, const void *f, double *rho, double *ux,
                      double *uy, double *th, double *part, hipStream_t st, int &nb)
 {
-    PLBM_DISPATCH(d->storage, launch_moments, p, d, f, rho, ux, uy, th, part, st, nb);
+    PLBM_DISPATCH(d, launch_moments, p, d, f, rho, ux, uy, th, part, st, nb);
 }
 
 // Plain streaming copy, 16 bytes per thread: the calibration kernel for

@@ -27,10 +27,11 @@ class Lattice:
 
     storage: "f64", "f32", "f16dev" or "bf16dev" (16-bit deviations from the
     rest state rho0 w_k with per-plane power-of-two scales; D2Q25 only).
+    rounding: "nearest" or "stochastic" (16-bit deviations only).
     """
 
     def __init__(self, dim, nx, ny=1, omega=1.0, storage="f64", device="cuda:0",
-                 rho0=1.0, theta0=None, zeta=None, velocities=None):
+                 rho0=1.0, theta0=None, zeta=None, velocities=None, rounding="nearest"):
         self.device = torch.device(device)
         if zeta is not None:
             self.desc = _plbm.desc_q3(dim, nx, ny, omega, storage, zeta=zeta)
@@ -41,6 +42,9 @@ class Lattice:
         if theta0 is not None:
             self.desc.theta0 = float(theta0)
         self.desc.rho0 = float(rho0)
+        self.desc.rounding = _plbm.ROUNDING[rounding]
+        if _plbm.buffer_elems(self.desc) == 0:
+            raise _plbm.PlbmError(_plbm.PLBM_EINVAL, "Lattice: rounding needs 16-bit storage")
         self.dim, self.nx, self.ny = dim, nx, (1 if dim == 1 else ny)
         self.dtype = _TORCH_DTYPE[self.desc.storage]
         n = _plbm.buffer_elems(self.desc)

@@ -156,6 +156,19 @@ def test_node_count_limit():
     assert _plbm.buffer_elems(d) == 0
 
 
+def test_rounding_mode_validation():
+    """Stochastic rounding applies to the 16-bit deviation forms only."""
+    buf, other = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f16dev")
+    d.rounding = _plbm.PLBM_ROUND_STOCHASTIC
+    assert _plbm.buffer_elems(d) == 25 * 64 * 64
+    d.rounding = 2
+    assert _plbm.buffer_elems(d) == 0
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f32")
+    d.rounding = _plbm.PLBM_ROUND_STOCHASTIC
+    assert _plbm.lib.plbm_step(ctypes.byref(d), buf, other, 1, None, None) == _plbm.PLBM_EINVAL
+
+
 def test_strerror():
     assert _plbm.strerror(0) == "ok"
     assert "non-finite" in _plbm.strerror(_plbm.PLBM_ENONFINITE)

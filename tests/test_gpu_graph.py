@@ -16,6 +16,10 @@ def _make(kind):
     if kind == "d2q25_f16dev":
         f = inputs.kelvin_helmholtz(300, 48, u0=0.08, delta=4.0, theta=0.35)
         mk = lambda: Lattice(2, 300, 48, omega=1.8, storage="f16dev", theta0=0.35).init(*f)
+    elif kind == "d2q25_bf16dev_sr":
+        f = inputs.kelvin_helmholtz(300, 48, u0=0.08, delta=4.0, theta=0.35)
+        mk = lambda: Lattice(2, 300, 48, omega=1.8, storage="bf16dev", theta0=0.35,
+                             rounding="stochastic").init(*f)
     elif kind == "d2q25_f64":
         f = inputs.random_fields(261, 20, seed=8)
         mk = lambda: Lattice(2, 261, 20, omega=1.6).init(*f)
@@ -35,8 +39,8 @@ def _make(kind):
     return mk
 
 
-@pytest.mark.parametrize("kind", ["d2q25_f16dev", "d2q25_f64", "d2q9_f32", "d2q49_f32",
-                                  "d1q5_f64", "d3q125_f32"])
+@pytest.mark.parametrize("kind", ["d2q25_f16dev", "d2q25_bf16dev_sr", "d2q25_f64", "d2q9_f32",
+                                  "d2q49_f32", "d1q5_f64", "d3q125_f32"])
 def test_captured_steps_replay_bitwise(kind):
     mk = _make(kind)
     lat, ref = mk(), mk()

@@ -27,8 +27,8 @@ pytestmark = pytest.mark.gpu
 EPS32 = np.finfo(np.float32).eps
 
 
-def _run_both(nx, ny, fields, omega, steps, storage="f64", theta0=None):
-    lat = Lattice(2, nx, ny, omega=omega, storage=storage, theta0=theta0)
+def _run_both(nx, ny, fields, omega, steps, storage="f64", theta0=None, rounding="nearest"):
+    lat = Lattice(2, nx, ny, omega=omega, storage=storage, theta0=theta0, rounding=rounding)
     lat.init(*fields)
     lat.step(steps)
     got = [t.cpu().numpy() for t in lat.moments()]
@@ -91,15 +91,22 @@ def test_step_f64_kelvin_helmholtz_literal_within_horizon():
     assert max(_field_errs(got, ref, 0.1)) < 1e-12
 
 
-def test_split_calls_are_bitwise_equal():
+@pytest.mark.parametrize("storage,rounding", [("f64", "nearest"), ("f16dev", "stochastic"),
+                                              ("bf16dev", "stochastic")])
+def test_split_calls_are_bitwise_equal(storage, rounding):
+    """Deterministic whatever the split of the steps into calls; for
+    stochastic rounding too, since its random bits hash the node, the
+    population and the value."""
     fields = inputs.random_fields(270, 20, seed=3)
-    a = Lattice(2, 270, 20, omega=1.6).init(*fields)
-    b = Lattice(2, 270, 20, omega=1.6).init(*fields)
+    kw = dict(omega=1.6, storage=storage, rounding=rounding,
+              theta0=0.35 if storage != "f64" else None)
+    a = Lattice(2, 270, 20, **kw).init(*fields)
+    b = Lattice(2, 270, 20, **kw).init(*fields)
     a.step(9)
     for _ in range(9):
         b.step(1)
     assert torch.equal(a.f, b.f)
-    c = Lattice(2, 270, 20, omega=1.6).init(*fields)
+    c = Lattice(2, 270, 20, **kw).init(*fields)
     c.step(9)
     assert torch.equal(a.f, c.f)
 
@@ -116,29 +123,36 @@ def test_step_f32_parity():
     assert max(errs) < steps * 200 * EPS32, errs
 
 
+@pytest.mark.parametrize("rounding", ["nearest", "stochastic"])
 @pytest.mark.parametrize("storage,half_ulp", [("f16dev", 2.0 ** -2), ("bf16dev", 2.0)])
-def test_step_dev_storage_parity(storage, half_ulp):
+def test_step_dev_storage_parity(storage, half_ulp, rounding):
     steps = 40
     th = 0.35
     fields = inputs.kelvin_helmholtz(300, 40, u0=0.1, theta=th)
-    lat, got, ref, _ = _run_both(300, 40, fields, 1.8, steps, storage=storage, theta0=th)
-    per_store = half_ulp * sum(lat.desc.scale[k] for k in range(25))
+    lat, got, ref, _ = _run_both(300, 40, fields, 1.8, steps, storage=storage, theta0=th,
+                                 rounding=rounding)
+    # one store rounds by at most half an ulp (nearest) or one ulp (stochastic)
+    ulps = 1.0 if rounding == "nearest" else 2.0
+    per_store = ulps * half_ulp * sum(lat.desc.scale[k] for k in range(25))
     bound = steps * per_store
     errs = _field_errs(got, ref, 1.0)
     assert errs[0] < bound and errs[3] < bound / 0.35, (errs, bound)
     assert errs[1] < 3 * bound and errs[2] < 3 * bound, (errs, bound)
 
 
+@pytest.mark.parametrize("rounding", ["nearest", "stochastic"])
 @pytest.mark.parametrize("storage,half_ulp", [("f16dev", 2.0 ** -2), ("bf16dev", 2.0)])
 @pytest.mark.parametrize("nx", [512, 300])     # whole 256-node tiles, and a ragged last tile
-def test_dev_storage_step_matches_oracle_step(storage, half_ulp, nx):
+def test_dev_storage_step_matches_oracle_step(storage, half_ulp, nx, rounding):
     """One step from the GPU's own 16-bit state, population by population:
     the oracle's FP64 step of the decoded state, within the rounding of the
-    stored deviation (half an ulp of |h| < 2^10, doubled for growth) plus
-    FP32 arithmetic."""
+    stored deviation (half an ulp of |h| < 2^10 for nearest, doubled for
+    growth, which also covers the one ulp of stochastic rounding) plus FP32
+    arithmetic."""
     ny, th = 24, 0.35
     fields = inputs.kelvin_helmholtz(nx, ny, u0=0.1, delta=3.0, theta=th)
-    lat = Lattice(2, nx, ny, omega=1.8, storage=storage, theta0=th).init(*fields)
+    lat = Lattice(2, nx, ny, omega=1.8, storage=storage, theta0=th,
+                  rounding=rounding).init(*fields)
     lat.step(3)
     pre = pulled_state(lat.f, lat)
     lat.step(1)
