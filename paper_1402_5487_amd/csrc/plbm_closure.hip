@@ -51,6 +51,18 @@ constexpr int NPARAM = 3 * LAYER_P;
 #ifndef PLBM_WG_ROWS
 #define PLBM_WG_ROWS 16
 #endif
+#ifndef PLBM_CONV_BLOCKS
+#define PLBM_CONV_BLOCKS 256       // target block count of the convolution launches
+#endif
+#ifndef PLBM_CONV_MAX_ROWS
+#define PLBM_CONV_MAX_ROWS 16      // most output rows per convolution block
+#endif
+#ifndef PLBM_CONV_WAVES
+#define PLBM_CONV_WAVES 2          // waves per SIMD the convolution's registers must allow
+#endif
+#ifndef PLBM_CONV_BROWS_DIV
+#define PLBM_CONV_BROWS_DIV 2      // input-gradient blocks take rows / this
+#endif
 constexpr int WG_ROWS = PLBM_WG_ROWS;          // rows per weight-gradient block
 constexpr int WG_SEG = 64;                     // nodes per weight-gradient row segment
 
@@ -148,17 +160,78 @@ __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, 
 // A block covers 4 waves x 32 nodes of `rows` consecutive rows; each lane
 // keeps its 18 weight operands in registers across the rows (the weights
 // are the same for every node, and reloading them per row made the L1 read
-// traffic several times the activations').  conv_rows() picks the row count
-// that leaves about 512 blocks (measured best at 8 frames of 256^2, 1.5x
-// faster than one row per block; a single frame keeps one row per block).
+// traffic several times the activations').  The A operands of the three
+// input rows an output row reads (3 columns x 2 channel halves each) form a
+// ring in registers: the next output row reuses two of them and loads one
+// new input row, issued while the current row's MFMAs run (three times
+// fewer operand loads; the forward pass is 20 % faster).  conv_rows() picks
+// the row count that leaves about 256 blocks, at most 16 rows each
+// (measured best at 8 frames of 256^2; a single frame keeps one row per
+// block).
 inline int conv_rows(int nx, int ny, int frames)
 {
     const long long blocks1 = (long long)((nx / 32 + 3) / 4) * ny * frames;
-    return (int)std::max<long long>(1, std::min<long long>(8, blocks1 / 512));
+    return (int)std::max<long long>(1, std::min<long long>(PLBM_CONV_MAX_ROWS, blocks1 / PLBM_CONV_BLOCKS));
+}
+
+// A operands of one input row: columns x - 1, x, x + 1 (periodic) of the
+// lane's node, channel halves 0..15 and 16..31
+__device__ __forceinline__ void cl_load_row(const u16 *__restrict__ in, size_t fbase, int nx, int ny,
+                                            int ys, const int (&xs)[3], int kh, bf16x8 (&a)[3][2])
+{
+    ys += (ys < 0) ? ny : 0;
+    ys -= (ys >= ny) ? ny : 0;
+    const u16 *row = in + (fbase + (size_t)ys * nx) * CH + 8 * kh;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            a[d][h] = *reinterpret_cast<const bf16x8 *>(row + (size_t)xs[d] * CH + h * 16);
+}
+
+// Output row y with input rows y - 1, y, y + 1 in ring slots P, P + 1, P + 2
+// (mod 3).  The taps reading row y - 1 go first; when `more`, input row
+// y + 2 is then loaded into slot P while the other six MFMA pairs run.
+template <int MODE, int P>
+__device__ __forceinline__ void cl_conv_row(bf16x8 (&A)[3][3][2], const bf16x8 (&bw)[TAPS][2],
+                                            const u16 *__restrict__ in, const u16 *__restrict__ act,
+                                            void *__restrict__ out, size_t fbase, int nx, int ny, int y,
+                                            int x0, const int (&xs)[3], int l, float bj, bool more)
+{
+    const int kh = l >> 5, j = l & 31;
+    f32x16 acc = {};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {                 // input row y - 1 + r, ring slot P + r
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {             // input column x - 1 + d
+            // tap (ty, tx) of the kernel: the forward pass reads input y + ty - 1,
+            // the input gradient (mirrored kernel) input y - ty + 1
+            const int t = (MODE == 2) ? (2 - r) * 3 + (2 - d) : r * 3 + d;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[(P + r) % 3][d][h], bw[t][h], acc, 0, 0, 0);
+        }
+        if (r == 0 && more) cl_load_row(in, fbase, nx, ny, y + 2, xs, kh, A[P]);
+    }
+    // D[i][j]: i = node 8*(r/4) + 4*(l/32) + r%4, j = channel l%32
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
+        const size_t node = fbase + (size_t)y * nx + x0 + i;
+        float v = acc[r] + bj;
+        if (MODE == 0) {
+            reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(fmaxf(v, 0.f));
+        } else if (MODE == 1) {
+            reinterpret_cast<float *>(out)[node * CH + j] = v;
+        } else {
+            const float a = bf16_val(act[node * CH + j]);
+            reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(a > 0.f ? v : 0.f);
+        }
+    }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_cl_conv(const u16 *__restrict__ in, const u16 *__restrict__ wb,
+__global__ __launch_bounds__(256, PLBM_CONV_WAVES) void k_cl_conv(const u16 *__restrict__ in, const u16 *__restrict__ wb,
                                                  const float *__restrict__ bias,
                                                  const u16 *__restrict__ act, void *__restrict__ out,
                                                  int nx, int ny, int rows)
@@ -166,7 +239,9 @@ __global__ __launch_bounds__(256) void k_cl_conv(const u16 *__restrict__ in, con
     const int f = blockIdx.z;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int x0 = (blockIdx.x * 4 + wv) * 32;       // first node of this wave
-    if (x0 >= nx) return;
+    const int ybeg = blockIdx.y * rows;
+    if (x0 >= nx || ybeg >= ny) return;
+    const int yend = min(ybeg + rows, ny);
     const int row_i = l & 31, kh = l >> 5;            // A: node row_i, channels 8*kh..
     const size_t fbase = (size_t)f * ny * nx;
     // B: column (output channel) l & 31, k = 8*kh.. within each half
@@ -176,48 +251,26 @@ __global__ __launch_bounds__(256) void k_cl_conv(const u16 *__restrict__ in, con
 #pragma unroll
         for (int h = 0; h < 2; ++h)
             bw[t][h] = *reinterpret_cast<const bf16x8 *>(wb + ((size_t)t * CH + (l & 31)) * CH + h * 16 + 8 * kh);
-    const int j = l & 31;
-    const float bj = (MODE == 2) ? 0.f : bias[j];
+    const float bj = (MODE == 2) ? 0.f : bias[l & 31];
+    int xs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int x = x0 + row_i + d - 1;
+        x += (x < 0) ? nx : 0;
+        x -= (x >= nx) ? nx : 0;
+        xs[d] = x;
+    }
+    bf16x8 A[3][3][2];
+    cl_load_row(in, fbase, nx, ny, ybeg - 1, xs, kh, A[0]);
+    cl_load_row(in, fbase, nx, ny, ybeg, xs, kh, A[1]);
+    cl_load_row(in, fbase, nx, ny, ybeg + 1, xs, kh, A[2]);
 #pragma unroll 1
-    for (int rr = 0; rr < rows; ++rr) {
-        const int y = blockIdx.y * rows + rr;
-        if (y >= ny) break;
-        f32x16 acc = {};
-#pragma unroll
-        for (int t = 0; t < TAPS; ++t) {
-            int dy = t / 3 - 1, dx = t % 3 - 1;
-            if (MODE == 2) {
-                dy = -dy;
-                dx = -dx;
-            }
-            int ys = y + dy;
-            ys += (ys < 0) ? ny : 0;
-            ys -= (ys >= ny) ? ny : 0;
-            int xs = x0 + row_i + dx;
-            xs += (xs < 0) ? nx : 0;
-            xs -= (xs >= nx) ? nx : 0;
-            const u16 *src = in + (fbase + (size_t)ys * nx + xs) * CH;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(src + h * 16 + 8 * kh);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[t][h], acc, 0, 0, 0);
-            }
-        }
-        // D[i][j]: i = node 8*(r/4) + 4*(l/32) + r%4, j = channel l%32
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
-            const size_t node = fbase + (size_t)y * nx + x0 + i;
-            float v = acc[r] + bj;
-            if (MODE == 0) {
-                reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(fmaxf(v, 0.f));
-            } else if (MODE == 1) {
-                reinterpret_cast<float *>(out)[node * CH + j] = v;
-            } else {
-                const float a = bf16_val(act[node * CH + j]);
-                reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(a > 0.f ? v : 0.f);
-            }
-        }
+    for (int y = ybeg; y < yend; y += 3) {
+        cl_conv_row<MODE, 0>(A, bw, in, act, out, fbase, nx, ny, y, x0, xs, l, bj, y + 1 < yend);
+        if (y + 1 >= yend) break;
+        cl_conv_row<MODE, 1>(A, bw, in, act, out, fbase, nx, ny, y + 1, x0, xs, l, bj, y + 2 < yend);
+        if (y + 2 >= yend) break;
+        cl_conv_row<MODE, 2>(A, bw, in, act, out, fbase, nx, ny, y + 2, x0, xs, l, bj, y + 3 < yend);
     }
 }
 
@@ -949,7 +1002,7 @@ extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const
     const int crows = conv_rows(c->nx, c->ny, frames);
     const dim3 gc((c->nx / 32 + 3) / 4, (c->ny + crows - 1) / crows, frames);
     // the input-gradient pass (with its ReLU mask read) is fastest at half the rows
-    const int brows = std::max(1, crows / 2);
+    const int brows = std::max(1, crows / PLBM_CONV_BROWS_DIV);
     const dim3 gb((c->nx / 32 + 3) / 4, (c->ny + brows - 1) / brows, frames);
     const dim3 gw((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS), 1, frames);
     const int nwblk = (int)(gw.x * gw.z);

@@ -46,17 +46,25 @@ namespace {
 // Resident-workgroup cap of the 2D step, set by reserving LDS per workgroup
 // (160 KB per CU).  Fewer concurrent workgroups mean fewer DRAM rows open at
 // once; on MI355X at 4096^2 two workgroups per CU (8 waves) were fastest for
-// FP64 and FP32 storage and four for the 16-bit forms.
+// FP64 and FP32 storage and four for the 16-bit forms.  Stochastic rounding
+// adds ALU work per population and wants more waves to hide it: five
+// workgroups per CU (5.5 % faster than four).
 #ifndef PLBM_LDS_CAP_WIDE
 #define PLBM_LDS_CAP_WIDE (80 * 1024)
 #endif
 #ifndef PLBM_LDS_CAP_16
 #define PLBM_LDS_CAP_16 (40 * 1024)
 #endif
+#ifndef PLBM_LDS_CAP_16SR
+#define PLBM_LDS_CAP_16SR (27 * 1024)
+#endif
 
 constexpr int Q = 5;            // velocities per axis compiled into the kernels
 constexpr int NQ = Q * Q;       // populations of the 2D tensor-product model
-constexpr int TX = 256;         // tile width = threads per block
+#ifndef PLBM_TX
+#define PLBM_TX 256
+#endif
+constexpr int TX = PLBM_TX;     // tile width = threads per block
 constexpr int TY = PLBM_TILE_Y; // tile height (rows walked by each thread)
 constexpr int NXCD = 8;         // accelerator complex dies on MI355X
 constexpr int RED_THREADS = 256;

@@ -353,7 +353,9 @@ int launch_step(const KParams &p, const plbm_desc *d, const void *src, void *dst
     clear_launch_error();
     if (d->dim == 2) {
         nblocks = grid_for(p.ntiles);
-        const size_t lds = sizeof(T) == 2 ? PLBM_LDS_CAP_16 : PLBM_LDS_CAP_WIDE;
+        const size_t lds = sizeof(T) == 2 ? (d->rounding == PLBM_ROUND_STOCHASTIC ? PLBM_LDS_CAP_16SR
+                                                                                 : PLBM_LDS_CAP_16)
+                                          : PLBM_LDS_CAP_WIDE;
         if (p.nv == 2)
             hipLaunchKernelGGL((k_step2d<S, 2, SUMS>), dim3(nblocks), dim3(TX), lds, st,
                                (const T *)src, (T *)dst, p, partials);
