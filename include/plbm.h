@@ -434,7 +434,7 @@ int plbm_closure_apply(plbm_closure *c, void *const *post, int frames, float bou
  * 0 input, 1 layer-1 output, 2 layer-2 output (bf16 NHWC x 32), 3 network
  * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs,
  * 7 the physical correction c (FP32 planes [frame][k][y][x]),
- * 8 dL/dm (FP32 planes [frame][j][y][x]), 9 the equilibrium shift of the
+ * 8 dL/dm (FP32 [frame][y][x][j], j = mass, x/y momentum, energy), 9 the equilibrium shift of the
  * last apply (FP64 planes [frame][k][y][x], population k of node x). */
 int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes);
 

@@ -133,7 +133,7 @@ class Closure:
         if which in (7, 9):
             return out.reshape(self.frames, 25, self.ny, self.nx)[:nf]
         if which == 8:
-            return out.reshape(self.frames, 4, self.ny, self.nx)[:nf]
+            return out.reshape(self.frames, self.ny, self.nx, 4).permute(0, 3, 1, 2)[:nf]
         return out.float().reshape(self.frames, self.ny, self.nx, CH)[:nf]
 
 

@@ -523,12 +523,15 @@ __global__ __launch_bounds__(256) void k_cl_mloss(const float *__restrict__ C, P
         }
         const float *d = static_cast<const float *>(target.p[f]);
         const size_t at = (size_t)y * nx + x;
+        float a[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const float r = m[j] - d[j * plane + at];
             lsum += nm.mw2[j] * r * r;
-            A[((size_t)f * 4 + j) * plane + at] = 2.f * inv_n * nm.mw2[j] * r;
+            a[j] = 2.f * inv_n * nm.mw2[j] * r;
         }
+        // node-interleaved, so that the push gathers one 16-byte vector per neighbour
+        reinterpret_cast<float4 *>(A)[(size_t)f * plane + at] = make_float4(a[0], a[1], a[2], a[3]);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
@@ -554,10 +557,9 @@ __global__ __launch_bounds__(256) void k_cl_mgrad(const float *__restrict__ A, c
         int xs = x + nm.ivx[k], ys = y + nm.ivy[k];
         xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
         ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
-        const size_t at = (size_t)ys * nx + xs;
-        const float *a = A + (size_t)f * 4 * plane + at;
+        const float4 a = reinterpret_cast<const float4 *>(A)[(size_t)f * plane + (size_t)ys * nx + xs];
         const float vx = nm.vx[k], vy = nm.vy[k];
-        t[k] = nm.out_scale[k] * (a[0] + vx * a[plane] + vy * a[2 * plane] + (vx * vx + vy * vy) * a[3 * plane]) +
+        t[k] = nm.out_scale[k] * (a.x + vx * a.y + vy * a.z + (vx * vx + vy * vy) * a.w) +
                reg2n * y3[node * CH + k];
     }
     project(t, nm);
@@ -783,7 +785,7 @@ struct plbm_closure {
     float *slices = nullptr;                   // their first-pass sums
     float *lpart = nullptr;                    // loss partials
     float *corr = nullptr;                     // c = s * Ph y, planes [f][k][y][x]
-    float *mres = nullptr;                     // (2/N) w r, planes [f][j][y][x]
+    float *mres = nullptr;                     // (2/N) w r, [f][y][x][j]
     double *shift = nullptr;                   // equilibrium shift, planes [f][k][y][x]
     KParams kp;                                // the coarse lattice's rule
     int nwblk = 0, nlblk = 0;
