@@ -1,0 +1,50 @@
+"""The benchmark's command-line contract, checked without a GPU: more than
+one GPU is refused with a message, the CPU baseline leg reports what the
+result line needs, and every default form names its arithmetic type."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+from paper_1402_5487_amd import inputs  # noqa: E402
+
+
+def _run(args, env=None):
+    e = dict(os.environ)
+    e.update(env or {})
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, timeout=120, env=e)
+
+
+def test_more_than_one_gpu_is_refused():
+    for args, env in ((["--gpus", "2"], None), (["--gpus", "8"], None), ([], {"WORLD_SIZE": "2"})):
+        r = _run(args, env)
+        assert r.returncode != 0
+        assert "one GPU" in r.stderr
+        assert r.stdout.strip() == ""          # no result line
+
+
+def test_cpu_baseline_leg():
+    n = 24
+    out = bench.cpu_baseline(n, inputs.kelvin_helmholtz(n, n, u0=0.1, theta=0.35), 2)
+    assert out["kind"] == "oracle" and out["unit"] == "MLUPS"
+    assert out["value"] > 0 and np.isfinite(out["value"])
+    assert isinstance(out["cores"], int) and out["cores"] >= 1
+    assert "steps" in out["sample"]
+
+
+def test_default_forms_have_a_compute_dtype(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    args = bench.parse()
+    for f in args.forms.split(","):
+        assert f in bench.COMPUTE_DTYPE
+    assert args.gpus == 1 and args.steps > 0 and args.warmup >= 0
+
+
+def test_kernel_hash_is_stable():
+    assert bench.kernel_hash() == bench.kernel_hash()
+    assert len(bench.kernel_hash()) == 16
