@@ -19,9 +19,9 @@
  *    streaming.  The 1D rule uses q1d velocities in the paper's order
  *    (v_1 = 0, v_2,3 = +-a, v_4,5 = +-b, Sec. 2.4); the 2D model is the tensor
  *    product, population k = i + q1d * j moving with (v_i, v_j).  The device
- *    kernels are compiled for q1d = 5 and a symmetric set (0, a, -a, b, -b)
- *    with |a|, |b| <= 3; other sets are accepted by plbm_coeffs only and make
- *    the device calls return PLBM_EUNSUPPORTED.
+ *    kernels take 3 to 7 distinct integer velocities with |v| <= 3 (which
+ *    model a set selects: see plbm_desc); plbm_coeffs alone takes any real
+ *    set of up to PLBM_MAX_Q1D velocities.
  *
  * Population layout in HBM (structure of arrays at row granularity)
  * ----------------------------------------------------------------------
@@ -65,7 +65,7 @@ typedef enum plbm_status {
 } plbm_status;
 
 typedef enum plbm_bc {
-    PLBM_BC_PERIODIC = 0,    /* dim 2 */
+    PLBM_BC_PERIODIC = 0,    /* dims 2 and 3 */
     PLBM_BC_ZEROGRAD = 1     /* dim 1: ghosts copy the edge node */
 } plbm_bc;
 
@@ -209,7 +209,9 @@ int plbm_init3(const plbm_desc *d, const double *rho, const double *ux,
  * Without sums the call only launches kernels on `stream` (no allocation,
  * copy or synchronisation), so it can be recorded into a HIP graph.
  * Errors: PLBM_EINVAL (aliasing or null buffers, bad descriptor),
- * PLBM_ENONFINITE (sums requested and not finite), PLBM_EHIP.
+ * PLBM_EUNSUPPORTED (16-bit storage in 1D or 3D, a velocity set the
+ * kernels do not take), PLBM_ENONFINITE (sums requested and not finite),
+ * PLBM_EHIP.
  */
 int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
               double *sums, void *stream);
@@ -223,7 +225,8 @@ int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
  *   sums               : NULL or a host pointer to 4 doubles: FP64 sums over
  *                        the nodes of that state (as for plbm_step).
  *                        Asking for sums synchronises `stream`.
- * Errors: PLBM_EINVAL, PLBM_ENONFINITE, PLBM_EHIP.
+ * dim 3 descriptors take plbm_moments3 instead (PLBM_EINVAL here).
+ * Errors: PLBM_EINVAL, PLBM_EUNSUPPORTED, PLBM_ENONFINITE, PLBM_EHIP.
  */
 int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,
                  double *uy, double *theta, double *sums, void *stream);
@@ -434,8 +437,9 @@ int plbm_closure_apply(plbm_closure *c, void *const *post, int frames, float bou
  * 0 input, 1 layer-1 output, 2 layer-2 output (bf16 NHWC x 32), 3 network
  * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs,
  * 7 the physical correction c (FP32 planes [frame][k][y][x]),
- * 8 dL/dm (FP32 [frame][y][x][j], j = mass, x/y momentum, energy), 9 the equilibrium shift of the
- * last apply (FP64 planes [frame][k][y][x], population k of node x). */
+ * 8 dL/dm (FP32 [frame][y][x][j], j = mass, x and y momentum, energy),
+ * 9 the equilibrium shift of the last apply (FP64 planes [frame][k][y][x],
+ * population k of node x). */
 int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes);
 
 /*
