@@ -68,8 +68,8 @@ def parse():
                     help="run only the batching form (for profilers)")
     ap.add_argument("--closure-iters", type=int, default=2000,
                     help="training iterations of the learned closure (0 skips it)")
-    ap.add_argument("--closure-train-seeds", type=int, default=100)
-    ap.add_argument("--closure-held-seeds", type=int, default=10)
+    ap.add_argument("--closure-train-seeds", type=int, default=200)
+    ap.add_argument("--closure-held-seeds", type=int, default=20)
     ap.add_argument("--q9-forms", default="q9f64,q9f32",
                     help="D2Q9 isothermal (zeta = 4) forms timed beside the D2Q25 ones "
                          "(empty: none)")

@@ -236,7 +236,7 @@ def forward_rate(ex, reps=20):
     return ms, flops / (ms * 1e-3) / 1e12
 
 
-def run(n_coarse=256, factor=4, train_seeds=range(100), held_seeds=range(200, 210),
+def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 220),
         per_seed=10, horizon=500, iters=2000, batch=8, lr=1e-3, judge_steps=500,
         judge_every=50, input_noise=0.5, kmin=3, log=None):
     """The full learned-closure experiment: generate, train, judge."""
