@@ -276,70 +276,78 @@ __global__ __launch_bounds__(256, PLBM_CONV_WAVES) void k_cl_conv(const u16 *__r
 
 // ---------------------------------------------------------------------------
 // Weight gradient: dW[t][o][i] = sum_p dz[p][o] * a[p + d_t][i], db[o] = sum_p dz[p][o].
-// A 32x32x16 MFMA takes 8 consecutive nodes of one channel per lane, so the
-// node-major activations are transposed through LDS: dz channel-major, and
-// the input rows y-1, y, y+1 channel-major in three copies shifted by
-// dx = -1, 0, +1, so that every operand is one aligned 16-byte LDS read.  The
-// input rows form a ring in LDS, so each row of the block loads one new
+// A 32x32x16 MFMA takes 8 consecutive nodes of one channel per lane (the
+// contraction runs over nodes).  dz and the input rows y-1, y, y+1 sit in
+// LDS node-major, as they are in memory (16-byte writes), and each operand
+// is read with two of gfx950's transposing LDS reads (ds_read_b64_tr_b16).
+// Within each group of 16 lanes such a read gives lane 4a + b the b-th
+// 16-bit element of the 8-byte chunks that lanes a, a + 4, a + 8, a + 12
+// address.  Lane j of a group addresses node q + j/4, channels c + 4 (j%4),
+// so lane 4a + b receives nodes q .. q + 3 of channel c + 4a + b: the
+// operand layout.  An x shift of the input is an offset of the node index.
+// The input rows form a ring in LDS, so each row of the block loads one new
 // input row.  Block = WG_SEG nodes x WG_ROWS rows of one frame; wave w owns
 // taps w, w+4, w+8.  The next row's global loads are issued before the
 // current row's MFMAs.
 // ---------------------------------------------------------------------------
-constexpr int WG_LD = WG_SEG + 8;               // LDS row pitch: 144 B, 16-byte aligned
-constexpr int WG_AVEC = (WG_SEG + 2) * CH / 8;  // 16-byte vectors of one input row (66 nodes)
+constexpr int WG_AN = WG_SEG + 2;               // nodes of one input row: x0 - 1 .. x0 + WG_SEG
+constexpr int WG_AVEC = WG_AN * CH / 8;         // 16-byte vectors of one input row
 
-// One input row (nodes x0 - 1 .. x0 + WG_SEG, vectors t and 256 + t of this
-// thread) and one dz row segment (node t/4, channels 8 (t%4) ..).
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+
+// One input row (vectors t and 256 + t of this thread) and one dz row
+// segment (node t/4, channels 8 (t%4) ..).
 struct WgRegs {
-    uint4 dz;
-    uint4 a[2];
+    uint4 dz, a0, a1;
 };
 
+// vector i of an input row: node x0 - 1 + i / 4, channels 8 (i % 4) ..
+__device__ __forceinline__ uint4 wg_load_vec(const u16 *__restrict__ a, size_t fbase, int nx, int x0, int y,
+                                             int i)
+{
+    int xs = x0 + (i >> 2) - 1;
+    xs += (xs < 0) ? nx : 0;
+    xs -= (xs >= nx) ? nx : 0;
+    return *reinterpret_cast<const uint4 *>(a + (fbase + (size_t)y * nx + xs) * CH + (i & 3) * 8);
+}
+
 __device__ __forceinline__ void wg_load_a(const u16 *__restrict__ a, size_t fbase, int nx, int ny, int x0, int y,
-                                          uint4 (&v)[2])
+                                          uint4 &v0, uint4 &v1)
 {
     y += (y < 0) ? ny : 0;
     y -= (y >= ny) ? ny : 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = threadIdx.x + 256 * h;
-        if (i < WG_AVEC) {
-            int xs = x0 + (i >> 2) - 1;
-            xs += (xs < 0) ? nx : 0;
-            xs -= (xs >= nx) ? nx : 0;
-            v[h] = *reinterpret_cast<const uint4 *>(a + (fbase + (size_t)y * nx + xs) * CH + (i & 3) * 8);
-        }
-    }
+    v0 = wg_load_vec(a, fbase, nx, x0, y, threadIdx.x);
+    if (threadIdx.x + 256 < WG_AVEC) v1 = wg_load_vec(a, fbase, nx, x0, y, threadIdx.x + 256);
 }
 
-// input row -> LDS slot, transposed, in the three x shifts
-__device__ __forceinline__ void wg_store_a(u16 (*slot)[CH][WG_LD], const uint4 (&v)[2])
+// input row -> LDS slot, node-major (node m is x0 - 1 + m)
+__device__ __forceinline__ void wg_store_a(u16 (*slot)[CH], const uint4 &v0, const uint4 &v1)
 {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int i = threadIdx.x + 256 * h;
-        if (i < WG_AVEC) {
-            const int m = i >> 2, c0 = (i & 3) * 8;      // m: node x0 - 1 + m
-            const u16 *e = reinterpret_cast<const u16 *>(&v[h]);
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int n = m - dx;                    // copy dx holds node x0 + n + dx - 1
-                if (n >= 0 && n < WG_SEG) {
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) slot[dx][c0 + k][n] = e[k];
-                }
-            }
-        }
-    }
+    const int i = threadIdx.x;
+    *reinterpret_cast<uint4 *>(&slot[i >> 2][(i & 3) * 8]) = v0;
+    if (i + 256 < WG_AVEC) *reinterpret_cast<uint4 *>(&slot[(i + 256) >> 2][((i + 256) & 3) * 8]) = v1;
+}
+
+// MFMA operand of lane l from a node-major LDS array: nodes
+// n0 + 8 (l / 32) .. + 7 of channel l % 32
+__device__ __forceinline__ bf16x8 wg_operand(const u16 (*rows)[CH], int n0, int l)
+{
+    const int j = l & 15;
+    const int node = n0 + 8 * (l >> 5) + (j >> 2);
+    const int ch = 16 * ((l >> 4) & 1) + 4 * (j & 3);
+    const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)&rows[node][ch]);
+    const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)&rows[node + 4][ch]);
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
 __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, const u16 *__restrict__ dz,
                                                   int nx, int ny, float *__restrict__ part)
 {
-    __shared__ __attribute__((aligned(16))) u16 sdz[CH][WG_LD];
-    // a ring of three input rows, each channel-major in three x shifts:
-    // row yy sits in slot (yy - y0 + 1) % 3
-    __shared__ __attribute__((aligned(16))) u16 sa[3][3][CH][WG_LD];
+    __shared__ __attribute__((aligned(16))) u16 sdz[WG_SEG][CH];
+    // a ring of three input rows: row yy sits in slot (yy - y0 + 1) % 3
+    __shared__ __attribute__((aligned(16))) u16 sa[3][WG_AN][CH];
+    __shared__ float bred[4][4][8];
     const int f = blockIdx.z;
     const int segs = nx / WG_SEG;
     const int x0 = (blockIdx.x % segs) * WG_SEG;
@@ -350,60 +358,63 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
     f32x16 acc[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[q] = f32x16{};
-    float bsum = 0.f;
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // node t/4, channels 8 (t%4) ..
     {
-        uint4 v[2];
-        wg_load_a(a, fbase, nx, ny, x0, y0 - 1, v);
-        wg_store_a(sa[0], v);
-        wg_load_a(a, fbase, nx, ny, x0, y0, v);
-        wg_store_a(sa[1], v);
+        uint4 v0 = {}, v1 = {};
+        wg_load_a(a, fbase, nx, ny, x0, y0 - 1, v0, v1);
+        wg_store_a(sa[0], v0, v1);
+        wg_load_a(a, fbase, nx, ny, x0, y0, v0, v1);
+        wg_store_a(sa[1], v0, v1);
     }
-    WgRegs R;
+    WgRegs R = {};
     R.dz = *reinterpret_cast<const uint4 *>(dz + (fbase + (size_t)y0 * nx + x0 + (t >> 2)) * CH + (t & 3) * 8);
-    wg_load_a(a, fbase, nx, ny, x0, y0 + 1, R.a);
+    wg_load_a(a, fbase, nx, ny, x0, y0 + 1, R.a0, R.a1);
 
 #pragma unroll 1
     for (int r = 0; r < rows; ++r) {
         const int y = y0 + r;
         __syncthreads();                 // the previous row's LDS reads are done
+        *reinterpret_cast<uint4 *>(&sdz[t >> 2][(t & 3) * 8]) = R.dz;
         {
-            const int node = t >> 2, c0 = (t & 3) * 8;
-            const u16 *e = reinterpret_cast<const u16 *>(&R.dz);
+            const uint32_t w4[4] = {R.dz.x, R.dz.y, R.dz.z, R.dz.w};
 #pragma unroll
-            for (int k = 0; k < 8; ++k) sdz[c0 + k][node] = e[k];
+            for (int k = 0; k < 8; ++k) bsum[k] += bf16_val((u16)(w4[k >> 1] >> (16 * (k & 1))));
         }
-        wg_store_a(sa[(r + 2) % 3], R.a);          // row y + 1
+        wg_store_a(sa[(r + 2) % 3], R.a0, R.a1);   // row y + 1
         __syncthreads();
         if (r + 1 < rows) {
             R.dz = *reinterpret_cast<const uint4 *>(dz + (fbase + (size_t)(y + 1) * nx + x0 + (t >> 2)) * CH +
                                                     (t & 3) * 8);
-            wg_load_a(a, fbase, nx, ny, x0, y + 2, R.a);
-        }
-        if (wv == 0 && l < CH) {
-#pragma unroll
-            for (int k = 0; k < WG_SEG; k += 8) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(&sdz[l][k]);
-                const u16 *e = reinterpret_cast<const u16 *>(&q);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) bsum += bf16_val(e[m]);
-            }
+            wg_load_a(a, fbase, nx, ny, x0, y + 2, R.a0, R.a1);
         }
         // A = dz^T (row o = l&31, k = nodes), B = a_t (col i = l&31, k = nodes)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int tap = wv + 4 * q;
-            if (tap >= TAPS) break;
-            const int dy = tap / 3, dx = tap % 3;        // input row y + dy - 1
-            const int slot = (r + dy) % 3;
+        for (int kc = 0; kc < WG_SEG / 16; ++kc) {
+            const bf16x8 av = wg_operand(sdz, kc * 16, l);
 #pragma unroll
-            for (int kc = 0; kc < WG_SEG / 16; ++kc) {
-                const int n0 = kc * 16 + 8 * (l >> 5);
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&sdz[l & 31][n0]);
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sa[slot][dx][l & 31][n0]);
+            for (int q = 0; q < 3; ++q) {
+                const int tap = wv + 4 * q;
+                if (tap >= TAPS) break;
+                const int dy = tap / 3, dx = tap % 3;    // input row y + dy - 1, node x + dx - 1
+                const int slot = (r + dy) % 3;
+                // output node x0 + n reads input node x0 + n + dx - 1, LDS node n + dx
+                const bf16x8 bv = wg_operand(sa[slot], kc * 16 + dx, l);
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[q], 0, 0, 0);
             }
         }
     }
+    // bias: sum the per-thread channel sums over the 16 nodes of the wave
+    // (lanes 4 n + q), then over the four waves, in a fixed order
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int off = 4; off < 64; off <<= 1) bsum[k] += __shfl_xor(bsum[k], off, 64);
+    }
+    if (l < 4) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) bred[wv][l][k] = bsum[k];
+    }
+    __syncthreads();
     // partials: [block][t][o][i] then [block][bias o]
     const size_t nblk = (size_t)gridDim.x * gridDim.y * gridDim.z;
     const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -417,7 +428,10 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
             part[blk * LAYER_W + ((size_t)tap * CH + o) * CH + (l & 31)] = acc[q][r];
         }
     }
-    if (wv == 0 && l < CH) part[nblk * LAYER_W + blk * CH + l] = bsum;
+    if (t < CH) {
+        const int q = t >> 3, k = t & 7;
+        part[nblk * LAYER_W + blk * CH + t] = (bred[0][q][k] + bred[1][q][k]) + (bred[2][q][k] + bred[3][q][k]);
+    }
 }
 
 // Sum the block partials in a fixed order into the flat gradient of one
