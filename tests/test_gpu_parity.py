@@ -253,11 +253,14 @@ def test_checkpoint_resume_is_bitwise():
 # populations equal the oracle's collision of the same pulled state
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
-def test_full_size_sampled_nodes(storage):
+@pytest.mark.parametrize("storage,rounding", [("f64", "nearest"), ("f32", "nearest"), ("f16dev", "nearest"),
+                                              ("bf16dev", "nearest"), ("f16dev", "stochastic"),
+                                              ("bf16dev", "stochastic")])
+def test_full_size_sampled_nodes(storage, rounding):
     n = 4096
+    dev = storage.endswith("dev")
     fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80, theta=0.35)
-    lat = Lattice(2, n, n, omega=1.8, storage=storage, theta0=0.35 if storage == "f16dev" else None)
+    lat = Lattice(2, n, n, omega=1.8, storage=storage, theta0=0.35 if dev else None, rounding=rounding)
     lat.init(*fields)
     lat.step(3)
     before = lat.f.clone()
@@ -272,7 +275,7 @@ def test_full_size_sampled_nodes(storage):
     dst = after.view(n, 25, n).transpose(0, 1)
     one = oracle.Lattice(2, 1, 1, omega=1.8)
     tol = 1e-14 if storage == "f64" else 64 * EPS32
-    if storage == "f16dev":
+    if dev:
         w = rest_weights(lat.desc.theta0)
         base = np.array([lat.desc.rho0 * w[k % 5] * w[k // 5] for k in range(25)],
                         dtype=np.float32).astype(np.float64)
@@ -285,9 +288,11 @@ def test_full_size_sampled_nodes(storage):
                         for k in range(25)]).reshape(25, 1, 1)
         post = one.step(pre, 1).ravel()       # 1x1 periodic lattice: pure collision
         got = np.array([dec(dst[k, y, x].double().item(), k) for k in range(25)])
-        if storage == "f16dev":
-            # half an ulp of the stored deviation (|h| < 2^10), doubled, plus FP32
-            bound = 2 * 2.0 ** -2 * scale + 64 * EPS32 * np.abs(post)
+        if dev:
+            # an ulp of the stored deviation (|h| < 2^10: 2^-1 in FP16, 2^2 in
+            # BF16), half of it for round to nearest, doubled, plus FP32
+            ulp = 2.0 ** -1 if storage == "f16dev" else 2.0 ** 2
+            bound = 2 * (ulp / 2 if rounding == "nearest" else ulp) * scale + 64 * EPS32 * np.abs(post)
             assert np.all(np.abs(got - post) <= bound), (y, x)
         else:
             assert np.abs(got - post).max() < tol * np.abs(post).max(), (y, x)
