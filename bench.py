@@ -47,6 +47,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def stored_traffic(form, path=TRAFFIC_FILE):
+    """HBM bytes per launch of the step in `form` from the stored counter
+    totals, or None when they are missing or were taken on other sources."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tr = json.load(fh)
+    if tr.get("kernel_sha256_16") != kernel_hash() or form not in tr.get("forms", {}):
+        return None
+    return tr["forms"][form]["hbm_bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,12 +445,7 @@ def main():
 
     head = "f16dev" if "f16dev" in results else forms[0]
     h = results[head]
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel_sha256_16") == kernel_hash() and head in tr.get("forms", {}):
-            traffic = tr["forms"][head]["hbm_bytes_per_launch"]
+    traffic = stored_traffic(head)
     cpu = None
     if not args.no_cpu:
         log("cpu oracle baseline")

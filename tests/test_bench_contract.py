@@ -2,6 +2,7 @@
 one GPU is refused with a message, the CPU baseline leg reports what the
 result line needs, and every default form names its arithmetic type."""
 import os
+import json
 import subprocess
 import sys
 
@@ -48,3 +49,26 @@ def test_default_forms_have_a_compute_dtype(monkeypatch):
 def test_kernel_hash_is_stable():
     assert bench.kernel_hash() == bench.kernel_hash()
     assert len(bench.kernel_hash()) == 16
+
+
+def test_traffic_is_reported_only_for_the_profiled_sources(tmp_path):
+    good = {"kernel_sha256_16": bench.kernel_hash(),
+            "forms": {"f16dev": {"hbm_bytes_per_launch": 123}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(good))
+    assert bench.stored_traffic("f16dev", str(p)) == 123
+    assert bench.stored_traffic("f32", str(p)) is None
+    p.write_text(json.dumps(dict(good, kernel_sha256_16="0" * 16)))
+    assert bench.stored_traffic("f16dev", str(p)) is None
+    assert bench.stored_traffic("f16dev", str(tmp_path / "missing.json")) is None
+
+
+def test_stored_counters_match_the_algorithmic_bytes():
+    """The committed counter totals: every step form moves its algorithmic
+    bytes (50 populations of its element size per node, 4096^2 nodes) to
+    within 3 %."""
+    with open(bench.TRAFFIC_FILE) as fh:
+        tr = json.load(fh)
+    for form, v in tr["forms"].items():
+        assert v["algorithmic_bytes_per_launch"] == 50 * {"f64": 8, "f32": 4}.get(form, 2) * 4096 ** 2
+        assert abs(v["hbm_over_algorithmic"] - 1) < 0.03, form
