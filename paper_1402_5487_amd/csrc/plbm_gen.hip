@@ -123,6 +123,17 @@ __device__ __forceinline__ void sums_gen2d(const C (&f)[Q1 * Q1], const GenParam
 // caps the resident workgroups at the best measured count.
 template <int Q1>
 constexpr bool gen_nt_loads() { return Q1 <= 5; }
+// Sets whose first velocity is 0 (Z0): only that column is loaded
+// non-temporally, since it reads exactly the wave's own nodes while the
+// shifted columns' window edges are read again by the neighbouring wave.
+#ifndef PLBM_GEN_Z0_NT
+#define PLBM_GEN_Z0_NT 1
+#endif
+template <int Q1, bool Z0>
+constexpr unsigned gen_nt_mask()
+{
+    return (Z0 && PLBM_GEN_Z0_NT) ? 1u : (gen_nt_loads<Q1>() ? (1u << Q1) - 1 : 0u);
+}
 template <int Q1, typename T>
 constexpr size_t gen_lds_cap() { return (sizeof(T) == 4 && Q1 <= 4) ? 40 * 1024 : 53 * 1024; }
 
@@ -134,7 +145,7 @@ __device__ __forceinline__ T load_g(const T *p)
 }
 
 // Pull-gather of node (xb, y): f_k = src_k(x - v_i, y - v_j), k = i + Q1 j.
-template <int Q1, typename T, typename C>
+template <int Q1, typename T, typename C, bool Z0 = false>
 __device__ __forceinline__ void gather_gen2d(const T *__restrict__ src, const GenParams &p, int xb, int y,
                                              C (&f)[Q1 * Q1])
 {
@@ -149,7 +160,10 @@ __device__ __forceinline__ void gather_gen2d(const T *__restrict__ src, const Ge
         const int ys = wrap_g(y - p.sx[j], p.ny);
         const T *base = src + (ys * rowelems + (long long)(Q1 * j) * nx);
 #pragma unroll
-        for (int i = 0; i < Q1; ++i) f[i + Q1 * j] = (C)load_g<gen_nt_loads<Q1>()>(&base[lo[i]]);
+        for (int i = 0; i < Q1; ++i) {
+            if ((gen_nt_mask<Q1, Z0>() >> i) & 1) f[i + Q1 * j] = (C)load_g<true>(&base[lo[i]]);
+            else f[i + Q1 * j] = (C)load_g<false>(&base[lo[i]]);
+        }
     }
 }
 
@@ -174,7 +188,7 @@ __device__ __forceinline__ void collide_gen2d(C (&f)[Q1 * Q1], const GenParams &
         for (int i = 0; i < Q1; ++i) f[i + Q1 * j] = fma(keep, f[i + Q1 * j], rx[i] * ry[j]);
 }
 
-template <int Q1, typename T, bool SUMS>
+template <int Q1, typename T, bool SUMS, bool Z0>
 __global__ __launch_bounds__(TX) void k_step_gen2d(const T *__restrict__ src, T *__restrict__ dst, GenParams p,
                                                    double *__restrict__ partials)
 {
@@ -188,7 +202,7 @@ __global__ __launch_bounds__(TX) void k_step_gen2d(const T *__restrict__ src, T 
         const int y = tile / p.tiles_x;
         const int xb = (tile - y * p.tiles_x) * TX + threadIdx.x;
         C f[NG];
-        gather_gen2d<Q1, T, C>(src, p, xb, y, f);
+        gather_gen2d<Q1, T, C, Z0>(src, p, xb, y, f);
         collide_gen2d<Q1, C>(f, p);
         if (xb < p.nx) {
             if constexpr (SUMS) {
@@ -449,9 +463,12 @@ int gen_finish_sums(double *dev, int nblocks, double *host, hipStream_t st)
 template <int Q1, typename T, bool SUMS>
 void gen_launch(const GenParams &p, const T *src, T *dst, double *part, hipStream_t st)
 {
-    if (p.dim == 2)
-        hipLaunchKernelGGL((k_step_gen2d<Q1, T, SUMS>), dim3(grid_g(p)), dim3(TX), (gen_lds_cap<Q1, T>()), st, src,
-                           dst, p, part);
+    if (p.dim == 2 && p.sx[0] == 0)
+        hipLaunchKernelGGL((k_step_gen2d<Q1, T, SUMS, true>), dim3(grid_g(p)), dim3(TX), (gen_lds_cap<Q1, T>()), st,
+                           src, dst, p, part);
+    else if (p.dim == 2)
+        hipLaunchKernelGGL((k_step_gen2d<Q1, T, SUMS, false>), dim3(grid_g(p)), dim3(TX), (gen_lds_cap<Q1, T>()), st,
+                           src, dst, p, part);
     else
         hipLaunchKernelGGL((k_step_gen1d<Q1, T, SUMS>), dim3(grid_g(p)), dim3(TX), 0, st, src, dst, p, part);
 }
