@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--d3-size", type=int, default=256)
     ap.add_argument("--d3-only", action="store_true",
                     help="time only the D3Q125 forms and print their line")
+    ap.add_argument("--kh1024-steps", type=int, default=10000,
+                    help="steps of the FP32 1024x1024 KH run compared with FP64 (0 skips it)")
     ap.add_argument("--closure-only", action="store_true",
                     help="run only the learned-closure experiment")
     return ap.parse_args()
@@ -254,6 +256,20 @@ def accuracy(forms, n, fields, steps, theta):
                         "theta": float((mom[3] - ref[3]).abs().max()),
                         "finite": bool(torch.isfinite(mom[0]).all())}
         del mom
+    return out
+
+
+def kh1024_form(args):
+    """The FP32 KH configuration at 1024^2 (delta = 12.8, theta = 0.35,
+    omega = 1.8): step rate, and the max abs error of rho, u, theta against
+    the FP64 run after --kh1024-steps steps."""
+    from paper_1402_5487_amd import inputs
+    n = 1024
+    fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80.0, theta=args.theta)
+    log(f"timing f32 {n}x{n} steps={args.steps} warmup={args.warmup}")
+    out = {"workload": f"D2Q25 thermal KH {n}x{n} periodic, FP32, theta={args.theta}, omega=1.8"}
+    out["f32"] = time_form("f32", n, fields, args.steps, args.warmup, args.theta)
+    out["f32"]["max_abs_err_vs_f64"] = accuracy(["f32"], n, fields, args.kh1024_steps, args.theta)["f32"]
     return out
 
 
@@ -427,6 +443,7 @@ def main():
 
     d3 = d3_forms(args)
     gen = gen_forms(args)
+    kh1024 = kh1024_form(args) if args.kh1024_steps > 0 else None
 
     acc = accuracy(forms, n, fields, args.accuracy_steps, args.theta) \
         if args.accuracy_steps > 0 else {}
@@ -481,6 +498,7 @@ def main():
         "vs_fp64_speedup": round(h["mlups"] / results["f64"]["mlups"], 3)
         if "f64" in results else None,
         "d2q9": rnd(d2q9) if d2q9 else None,
+        "kh1024": rnd(kh1024) if kh1024 else None,
         "d3q125": rnd(d3) if d3 else None,
         "general_sets": rnd(gen) if gen else None,
         "batch": rnd(batch) if batch else None,

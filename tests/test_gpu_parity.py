@@ -83,6 +83,16 @@ def test_step_f64_kelvin_helmholtz_stable_variant():
     assert max(_field_errs(got, ref, 0.1)) < 1e-12
 
 
+def test_step_f64_kelvin_helmholtz_1024():
+    """The 1024^2 KH configuration (delta = L/80 = 12.8, theta = 0.35,
+    omega = 1.8) in FP64 against the oracle: 300 steps (about 10 s of
+    oracle time; the 2000-step horizon holds too, measured once)."""
+    n = 1024
+    fields = inputs.kelvin_helmholtz(n, n, u0=0.1, delta=n / 80, theta=0.35)
+    lat, got, ref, f = _run_both(n, n, fields, 1.8, 300)
+    assert max(_field_errs(got, ref, 0.1)) < 1e-12
+
+
 def test_step_f64_kelvin_helmholtz_literal_within_horizon():
     """theta = 0.3 is linearly unstable (growth ~1.06 per step); 60 steps keep
     rounding differences ~1e-15 x 1.06^60 far below the bound."""
