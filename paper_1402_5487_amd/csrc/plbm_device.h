@@ -62,14 +62,14 @@ namespace {
 // Resident-workgroup cap of the 2D step, set by reserving LDS per workgroup
 // (160 KB per CU).  Fewer concurrent workgroups mean fewer DRAM rows open at
 // once; on MI355X at 4096^2 two workgroups per CU (8 waves) were fastest for
-// FP64 and FP32 storage and four for the 16-bit forms.  Stochastic rounding
-// adds ALU work per population and wants more waves to hide it: five
-// workgroups per CU (5.5 % faster than four).
+// FP64 and FP32 storage and five for the 16-bit forms (0.6-1.1 % faster than
+// four; three are 25 % slower).  Stochastic rounding adds ALU work per
+// population and also wants five (5.5 % faster than four).
 #ifndef PLBM_LDS_CAP_WIDE
 #define PLBM_LDS_CAP_WIDE (80 * 1024)
 #endif
 #ifndef PLBM_LDS_CAP_16
-#define PLBM_LDS_CAP_16 (40 * 1024)
+#define PLBM_LDS_CAP_16 (32 * 1024)
 #endif
 #ifndef PLBM_LDS_CAP_16SR
 #define PLBM_LDS_CAP_16SR (27 * 1024)
