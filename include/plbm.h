@@ -217,6 +217,32 @@ int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
               double *sums, void *stream);
 
 /*
+ * plbm_step_noalloc -- plbm_step without any device allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as plbm_step, for the descriptors of the symmetric five-velocity
+ * model (D1Q5 and D2Q25, every storage form); other descriptors return
+ * PLBM_EUNSUPPORTED.  The populations it writes are bitwise those of
+ * plbm_step; the sums agree to FP64 rounding (their partial sums are grouped
+ * differently).
+ * Scratch: the partial sums of a call that asks for sums live in a
+ * library-owned array in device memory, (8192 + 1) * 4 doubles (256 KiB),
+ * held by every GPU the library runs on until the process ends.  Its device
+ * address is looked up once per device, on the first call with that device
+ * current; the stream must belong to the current device.  A 2D sums step
+ * then runs at most 8192 workgroups, which walk all tiles.  Limit: a 1D
+ * lattice with sums may have at most 8192 * 256 = 2,097,152 nodes
+ * (PLBM_EINVAL beyond, before any launch); without sums no scratch is used
+ * and plbm_step's limits apply.
+ * Every call on one GPU shares that GPU's scratch and it keeps the last
+ * call's contents: calls that ask for sums and overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  Calls
+ * without sums do not touch it.
+ */
+int plbm_step_noalloc(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
+                      double *sums, void *stream);
+
+/*
  * plbm_moments -- macroscopic fields of the pre-collision state held by f
  * (pull, then rho = sum f, rho u = sum f v, 2 rho theta = sum f |v - u|^2 in
  * 2D and rho theta = sum f (v - u)^2 in 1D; one temperature for all axes).

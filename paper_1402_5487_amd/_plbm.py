@@ -82,6 +82,7 @@ def _load():
     lib.plbm_elem_bytes.restype = ctypes.c_size_t
     lib.plbm_init.argtypes = [P, vp, vp, vp, vp, vp, vp]
     lib.plbm_step.argtypes = [P, vp, vp, ctypes.c_int, D, vp]
+    lib.plbm_step_noalloc.argtypes = [P, vp, vp, ctypes.c_int, D, vp]
     lib.plbm_moments.argtypes = [P, vp, vp, vp, vp, vp, D, vp]
     lib.plbm_dev_scales.argtypes = [P, vp, vp, vp, vp, vp]
     lib.plbm_init3.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
@@ -100,7 +101,7 @@ lib = _load()
 EXPORTED = ("plbm_coeffs", "plbm_desc_default", "plbm_buffer_elems",
             "plbm_elem_bytes", "plbm_init", "plbm_step", "plbm_moments",
             "plbm_dev_scales", "plbm_strerror", "plbm_last_hip_error",
-            "plbm_stream_copy", "plbm_init3", "plbm_moments3")
+            "plbm_stream_copy", "plbm_init3", "plbm_moments3", "plbm_step_noalloc")
 
 
 def strerror(status):
@@ -202,6 +203,15 @@ def step(d, fa, fb, nsteps, want_sums, stream):
     sums = (ctypes.c_double * (5 if d.dim == 3 else 4))() if want_sums else None
     check(lib.plbm_step(ctypes.byref(d), _ptr(fa), _ptr(fb), int(nsteps), sums,
                         _stream(stream)), "plbm_step")
+    return list(sums) if want_sums else None
+
+
+def step_noalloc(d, fa, fb, nsteps, want_sums, stream):
+    """plbm_step_noalloc: as step(), with the sums' partials in the
+    library's static device scratch instead of an allocation."""
+    sums = (ctypes.c_double * 4)() if want_sums else None
+    check(lib.plbm_step_noalloc(ctypes.byref(d), _ptr(fa), _ptr(fb), int(nsteps), sums,
+                                _stream(stream)), "plbm_step_noalloc")
     return list(sums) if want_sums else None
 
 

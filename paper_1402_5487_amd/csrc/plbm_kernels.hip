@@ -36,8 +36,20 @@
 #include <cstdio>
 #include <cstring>
 
+#include <mutex>
+
 #include "plbm_device.h"
 #include "plbm_internal.h"
+
+// Scratch of plbm_step_noalloc: the per-workgroup FP64 partial sums of its
+// sums launch (at most NOALLOC_BLOCKS workgroups, four doubles each) and the
+// four reduced sums behind them.  Each GPU the library runs on holds its own
+// copy until the process ends.  Every workgroup of a sums launch writes its
+// own four partials before the reduction reads them, so nothing in it has to
+// start at zero.  Host code must not use this name as a device address: it
+// takes the address hipGetSymbolAddress returns for the current device.
+constexpr int NOALLOC_BLOCKS = 8192;
+static __device__ __align__(256) double scratch[(NOALLOC_BLOCKS + 1) * 4];
 
 namespace {
 
@@ -345,14 +357,21 @@ int finish_sums(double *dev, int nblocks, double *host, hipStream_t st)
     return PLBM_OK;
 }
 
+// Workgroups of a 2D launch over `tiles` tiles or row segments; max_blocks
+// caps the grid (the kernels walk the remaining tiles in a grid-stride loop).
+inline int grid_capped(long long tiles, int max_blocks)
+{
+    return std::min(grid_for(tiles), max_blocks);
+}
+
 template <class S, bool SUMS>
 int launch_step(const KParams &p, const plbm_desc *d, const void *src, void *dst, double *partials,
-                hipStream_t st, int &nblocks)
+                hipStream_t st, int &nblocks, int max_blocks = MAX_GRID)
 {
     using T = typename S::T;
     clear_launch_error();
     if (d->dim == 2) {
-        nblocks = grid_for(p.ntiles);
+        nblocks = grid_capped(p.ntiles, max_blocks);
         const size_t lds = sizeof(T) == 2 ? (d->rounding == PLBM_ROUND_STOCHASTIC ? PLBM_LDS_CAP_16SR
                                                                                  : PLBM_LDS_CAP_16)
                                           : PLBM_LDS_CAP_WIDE;
@@ -370,15 +389,22 @@ int launch_step(const KParams &p, const plbm_desc *d, const void *src, void *dst
     return launch_status();
 }
 
+// `scratch`: NULL, or a device buffer of (NOALLOC_BLOCKS + 1) * 4 doubles
+// that receives the partial sums instead of a stream-ordered allocation (the
+// sums launch then runs at most NOALLOC_BLOCKS workgroups).
 template <class S>
 int run_steps(const KParams &p, const plbm_desc *d, void *fa, void *fb, int nsteps, double *sums,
-              hipStream_t st)
+              hipStream_t st, double *scratch)
 {
     int nb = 0;
     for (int s = 0; s < nsteps; ++s) {
         const void *src = (s & 1) ? fb : fa;
         void *dst = (s & 1) ? fa : fb;
         const bool last = (s == nsteps - 1);
+        if (last && sums && scratch) {
+            const int rc = launch_step<S, true>(p, d, src, dst, scratch, st, nb, NOALLOC_BLOCKS);
+            return rc == PLBM_OK ? finish_sums(scratch, nb, sums, st) : rc;
+        }
         if (last && sums) {
             const int nblocks = d->dim == 2 ? grid_for(p.ntiles) : (p.nx + TX - 1) / TX;
             double *part = nullptr;
@@ -414,12 +440,13 @@ int launch_init(const KParams &p, const plbm_desc *d, const double *rho, const d
 
 template <class S>
 int launch_moments(const KParams &p, const plbm_desc *d, const void *f, double *rho, double *ux,
-                   double *uy, double *th, double *partials, hipStream_t st, int &nblocks)
+                   double *uy, double *th, double *partials, hipStream_t st, int &nblocks,
+                   int max_blocks)
 {
     using T = typename S::T;
     clear_launch_error();
     if (d->dim == 2) {
-        nblocks = grid_for((long long)((p.nx + TX - 1) / TX) * p.ny);
+        nblocks = grid_capped((long long)((p.nx + TX - 1) / TX) * p.ny, max_blocks);
         hipLaunchKernelGGL(k_moments2d<S>, dim3(nblocks), dim3(TX), 0, st, (const T *)f, p, rho,
                            ux, uy, th, partials);
     } else {
@@ -448,15 +475,16 @@ int init_dispatch(const KParams &p, const plbm_desc *d, const double *rho, const
 }
 
 int step_dispatch(const KParams &p, const plbm_desc *d, void *fa, void *fb, int n, double *sums,
-                  hipStream_t st)
+                  hipStream_t st, double *scratch = nullptr)
 {
-    PLBM_DISPATCH(d, run_steps, p, d, fa, fb, n, sums, st);
+    PLBM_DISPATCH(d, run_steps, p, d, fa, fb, n, sums, st, scratch);
 }
 
 int moments_dispatch(const KParams &p, const plbm_desc *d, const void *f, double *rho, double *ux,
-                     double *uy, double *th, double *part, hipStream_t st, int &nb)
+                     double *uy, double *th, double *part, hipStream_t st, int &nb,
+                     int max_blocks = MAX_GRID)
 {
-    PLBM_DISPATCH(d, launch_moments, p, d, f, rho, ux, uy, th, part, st, nb);
+    PLBM_DISPATCH(d, launch_moments, p, d, f, rho, ux, uy, th, part, st, nb, max_blocks);
 }
 
 // Plain streaming copy, 16 bytes per thread: the calibration kernel for
@@ -509,6 +537,57 @@ extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, d
         return PLBM_OK;
     }
     return step_dispatch(p, d, f_a, f_b, nsteps, sums, as_stream(stream));
+}
+
+namespace {
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+int scratch_for_current_device(double **out)
+{
+    int dev = -1;
+    int rc = hip_ok(hipGetDevice(&dev));
+    if (rc != PLBM_OK) return rc;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return PLBM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        rc = hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (rc != PLBM_OK) return rc;
+        if (!ptr) return PLBM_EHIP;
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return PLBM_OK;
+}
+} // namespace
+
+extern "C" int plbm_step_noalloc(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
+                                 double *sums, void *stream)
+{
+    if (d && d->dim == 3) return PLBM_EUNSUPPORTED;
+    if (plbm::gen_handles(d) || (d && d->q1d != Q)) return PLBM_EUNSUPPORTED;
+    KParams p;
+    int rc = make_params(d, p);
+    if (rc != PLBM_OK) return rc;
+    if (!f_a || !f_b || f_a == f_b || nsteps < 0) return PLBM_EINVAL;
+    // the 1D kernels run one workgroup per 256 nodes: at most NOALLOC_BLOCKS
+    // of them fit the scratch when sums are asked for
+    if (sums && d->dim == 1 && (p.nx + TX - 1) / TX > NOALLOC_BLOCKS) return PLBM_EINVAL;
+    if (!sums) return nsteps ? step_dispatch(p, d, f_a, f_b, nsteps, nullptr, as_stream(stream))
+                             : PLBM_OK;
+    double *scr = nullptr;
+    rc = scratch_for_current_device(&scr);
+    if (rc != PLBM_OK) return rc;
+    hipStream_t st = as_stream(stream);
+    if (nsteps > 0) return step_dispatch(p, d, f_a, f_b, nsteps, sums, st, scr);
+    int nb = 0;
+    rc = moments_dispatch(p, d, f_a, nullptr, nullptr, nullptr, nullptr, scr, st, nb,
+                          NOALLOC_BLOCKS);
+    return rc == PLBM_OK ? finish_sums(scr, nb, sums, st) : rc;
 }
 
 extern "C" int plbm_moments(const plbm_desc *d, const void *f, double *rho, double *ux,

@@ -97,6 +97,26 @@ def test_step_validates_before_launch():
                          None) == _plbm.PLBM_EUNSUPPORTED
 
 
+def test_step_noalloc_validates_before_launch():
+    """The allocation-free step refuses, before any device call, the models it
+    does not take and a 1D lattice with sums whose partials exceed its
+    scratch (8192 workgroups of 256 nodes)."""
+    lib = _plbm.lib
+    a, b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    s = (ctypes.c_double * 4)()
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f64")
+    assert lib.plbm_step_noalloc(ctypes.byref(d), a, a, 1, s, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step_noalloc(ctypes.byref(d), a, b, -1, s, None) == _plbm.PLBM_EINVAL
+    d1 = _plbm.desc_default(1, 8192 * 256 + 1, 1, 1.0, "f64")
+    assert lib.plbm_step_noalloc(ctypes.byref(d1), a, b, 1, s, None) == _plbm.PLBM_EINVAL
+    q9 = _plbm.desc_q3(2, 64, 64, 1.5, "f64", zeta=4.0)
+    assert lib.plbm_step_noalloc(ctypes.byref(q9), a, b, 1, s, None) == _plbm.PLBM_EUNSUPPORTED
+    d3 = _plbm.desc_3d(16, 16, 16, 1.5, "f64")
+    assert lib.plbm_step_noalloc(ctypes.byref(d3), a, b, 1, s, None) == _plbm.PLBM_EUNSUPPORTED
+    dg = _plbm.desc_general(2, 64, 64, 1.5, "f64", (0, 1, -1, 2, -3), theta0=None)
+    assert lib.plbm_step_noalloc(ctypes.byref(dg), a, b, 1, s, None) == _plbm.PLBM_EUNSUPPORTED
+
+
 def test_general_sets_are_validated_before_launch():
     """Asymmetric and q1d = 4, 6, 7 sets take the general kernels; what they
     cannot run is refused on the host: 16-bit storage, a table that is not
