@@ -40,6 +40,8 @@ def _load():
     lib.ref_moments.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, i]
     lib.ref_sums.argtypes = [i, i, i, i, _D, _D, _D]
     lib.ref_num_threads.argtypes = []
+    lib.ref_set_num_threads.argtypes = [i]
+    lib.ref_set_num_threads.restype = None
     lib.ref_init3.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D, _D]
     lib.ref_step3.argtypes = [i, i, i, i, _D, _D, d, _D, i]
     lib.ref_moments3.argtypes = [i, i, i, i, _D, _D, _D, _D, _D, _D, _D]
@@ -51,6 +53,12 @@ def _load():
 def num_threads():
     """Threads the oracle's OpenMP loops use."""
     return int(_load().ref_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (results are the same
+    for any count)."""
+    _load().ref_set_num_threads(int(n))
 
 
 def _p(a):

@@ -521,3 +521,14 @@ int ref_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the threads of the parallel loops (n >= 1); the results do not depend
+ * on it (each node and each push is computed by exactly one thread). */
+void ref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

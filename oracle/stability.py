@@ -47,11 +47,8 @@ def max_amplification(lat, rho, ux, uy, theta, nk=32):
     vy = np.array([lat.v[k // q1d] for k in range(lat.q)]) if lat.dim == 2 \
         else np.zeros(lat.q)
     ks = -np.pi + 2 * np.pi * np.arange(nk) / nk
-    best = 0.0
-    kys = ks if lat.dim == 2 else [0.0]
-    for kx in ks:
-        for ky in kys:
-            phase = np.exp(-1j * (kx * vx + ky * vy))
-            lam = np.abs(np.linalg.eigvals(phase[:, None] * J)).max()
-            best = max(best, float(lam))
-    return best
+    kys = ks if lat.dim == 2 else np.zeros(1)
+    kx, ky = np.meshgrid(ks, kys, indexing="ij")
+    phase = np.exp(-1j * (kx.reshape(-1, 1) * vx + ky.reshape(-1, 1) * vy))
+    # all wave vectors at once: G(kappa) = diag(phase(kappa)) J
+    return float(np.abs(np.linalg.eigvals(phase[:, :, None] * J[None])).max())

@@ -31,11 +31,19 @@ def test_more_than_one_gpu_is_refused():
 
 def test_cpu_baseline_leg():
     n = 24
-    out = bench.cpu_baseline(n, inputs.kelvin_helmholtz(n, n, u0=0.1, theta=0.35), 2)
+    fields = inputs.kelvin_helmholtz(n, n, u0=0.1, theta=0.35)
+    out, ref = bench.cpu_baseline(n, fields, 2)
     assert out["kind"] == "oracle" and out["unit"] == "MLUPS"
     assert out["value"] > 0 and np.isfinite(out["value"])
+    assert out["one_thread_mlups"] > 0
     assert isinstance(out["cores"], int) and out["cores"] >= 1
     assert "steps" in out["sample"]
+    # the moments handed to the FP64 anchor are the oracle's after the steps
+    import oracle
+    lat = oracle.Lattice(2, n, n, omega=1.8)
+    want = lat.moments(lat.step(lat.init(*fields), 2))
+    assert all(np.array_equal(a, b) for a, b in zip(ref, want))
+    assert oracle.num_threads() == out["cores"]     # thread count restored
 
 
 def test_default_forms_have_a_compute_dtype(monkeypatch):
@@ -72,3 +80,31 @@ def test_stored_counters_match_the_algorithmic_bytes():
     for form, v in tr["forms"].items():
         assert v["algorithmic_bytes_per_launch"] == 50 * {"f64": 8, "f32": 4}.get(form, 2) * 4096 ** 2
         assert abs(v["hbm_over_algorithmic"] - 1) < 0.03, form
+
+
+def test_first_nonfinite_stops_at_the_reported_step():
+    from paper_1402_5487_amd import _plbm
+    calls = []
+
+    def step(k):
+        calls.append(k)
+        if sum(calls) >= 75:
+            raise _plbm.PlbmError(_plbm.PLBM_ENONFINITE, "plbm_step")
+    assert bench.first_nonfinite(step, 1000, 25) == 75
+    calls.clear()
+    assert bench.first_nonfinite(lambda k: calls.append(k), 100, 25) is None and sum(calls) == 100
+
+
+def test_literal_predictions_from_the_oracle_growth():
+    """The CPU leg's predictions: the literal KH state grows (the oracle's
+    von Neumann factor exceeds 1) and each form's predicted blow-up step
+    follows its store rounding; a stable batch member (theta = 0.35) is
+    predicted never to blow up, an unstable one (theta = 0.25) within the run."""
+    lit = {"f64": {"first_nonfinite_step": 550}, "f16dev": {"first_nonfinite_step": 200}}
+    bench.predict_literal_kh(lit)
+    assert 1.05 < lit["growth_per_step"] < 1.2
+    assert lit["f64"]["predicted_step"] > lit["f16dev"]["predicted_step"] > 0
+    lb = {"steps": 2000, "_members": [(0.35, 0.05, 1.7), (0.25, 0.1, 1.85)], "_first": [None, 150]}
+    bench.predict_literal_batch(lb)
+    assert lb["predicted_unstable"] == 1 and lb["agree_with_prediction"] == 2
+    assert "_members" not in lb

@@ -135,3 +135,40 @@ def test_batch_conserves_mass_per_lattice():
         # the method; bounded by steps * eps32 relative
         assert abs(s1[0] / s0[i][0] - 1) < 40 * 2 * np.finfo(np.float32).eps
     b.close()
+
+
+def _forced_cache(path, specs, mode, w, r, lds=40 * 1024):
+    """An autotune cache that fixes every size class's tile shape and the grid
+    mode, so the batch runs them without timing anything."""
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    entries = [{"arch": arch, "storage": "f32", "class": c, "w": w, "r": r}
+               for c in sorted({max(nx, ny) for nx, ny, _ in specs})]
+    path.write_text(json.dumps({"entries": entries,
+                                "grid": {"arch": arch, "mode": mode, "lds": lds}}))
+    return path
+
+
+@pytest.mark.parametrize("mode", [2, 4])
+@pytest.mark.parametrize("w,r", [(64, 2), (256, 1)])
+def test_persistent_grid_modes_are_bitwise_equal(mode, w, r, tmp_path):
+    """Persistent grids (mode k: k workgroups per CU walking the tile list)
+    with more tiles than workgroups, so each workgroup runs the tile loop
+    several times: still bitwise equal to single lattices."""
+    specs = SPECS + [(1024, 1024, 1.75), (512, 512, 1.8), (320, 288, 1.65), (480, 96, 1.7)]
+    cache = _forced_cache(tmp_path / "t.json", specs, mode, w, r)
+    info = _bitwise_against_single(specs, 9, tune=cache)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert info["grid_mode"] == mode
+    assert info["tiles"] > 2 * mode * cus, info["tiles"]
+    assert all(v == (w, r) for v in info["classes"].values())
+
+
+@pytest.mark.parametrize("mode", [2, 4])
+def test_persistent_grid_on_the_work_list(mode, tmp_path):
+    """More sizes than the group table holds (48) take the device work list;
+    with a persistent grid each workgroup walks several work-list tiles."""
+    specs = [(100 + 2 * i, 90 + (i % 7), 1.5 + 0.008 * i) for i in range(50)]
+    cache = _forced_cache(tmp_path / "t.json", specs, mode, 64, 1)
+    info = _bitwise_against_single(specs, 7, tune=cache)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert info["grid_mode"] == mode and info["tiles"] > 2 * mode * cus, info

@@ -1,10 +1,19 @@
-"""Closure kernels at a shape whose launches exercise every path of their
-blocking: 64 x 250 nodes, 4 frames.  The convolution blocks then hold 3
-output rows each (about 256 blocks: the three-row register ring runs through
-all of its phases, with its row prefetch, and the last block of a frame is
-ragged), the input-gradient blocks 1 row, and the weight-gradient blocks 16
-rows with a ragged 10-row band at the end of each frame.  Bounds as in the
-closure kernel tests: FP32 accumulation of bf16 products, bf16 stores."""
+"""Closure kernels at shapes whose launches exercise every path of their
+blocking.  Bounds as in the closure kernel tests: FP32 accumulation of bf16
+products, bf16 stores.
+
+  * 64 x 250 nodes, 4 frames: the convolution blocks hold 3 output rows each
+    (about 256 blocks: the three-row register ring runs through all of its
+    phases, with its row prefetch, and the last block of a frame is ragged),
+    the input-gradient blocks 1 row, and the weight-gradient blocks 16 rows
+    with a ragged 10-row band at the end of each frame.  Only two of a
+    convolution block's four waves have nodes (64 = 2 x 32).
+  * 256 x 250 nodes, 8 frames (the width and frame count of the coarse
+    256^2 training batch): two convolution blocks per row band
+    (blockIdx.x > 0) with all four waves live, 15-row blocks with a ragged
+    10-row band, 7-row input-gradient blocks (ragged 5), and four 64-node
+    weight-gradient segments per row band.
+"""
 import numpy as np
 import pytest
 import torch
@@ -16,18 +25,28 @@ from paper_1402_5487_amd.lattice import Lattice
 
 pytestmark = pytest.mark.gpu
 
-NX, NY, FRAMES = 64, 250, 4
+SHAPES = [(64, 250, 4), (256, 250, 8)]
 BF = 2.0 ** -8
 
 
-def test_conv_row_blocking_matches_the_shape():
-    # the launch arithmetic this test relies on (target 256 blocks, 16 rows at most)
-    blocks1 = ((NX // 32 + 3) // 4) * NY * FRAMES
-    assert max(1, min(16, blocks1 // 256)) == 3 and NY % 3 != 0 and NY % 16 != 0
+def _conv_rows(nx, ny, frames):
+    # the launch arithmetic of the convolutions (target 256 blocks, 16 rows at most)
+    blocks1 = ((nx // 32 + 3) // 4) * ny * frames
+    return max(1, min(16, blocks1 // 256))
 
 
-@pytest.fixture(scope="module")
-def run():
+def test_conv_row_blocking_matches_the_shapes():
+    r0 = _conv_rows(*SHAPES[0])
+    assert r0 == 3 and SHAPES[0][1] % r0 != 0 and SHAPES[0][1] % 16 != 0
+    r1 = _conv_rows(*SHAPES[1])
+    assert r1 == 15 and SHAPES[1][1] % r1 != 0 and SHAPES[1][1] % (r1 // 2) != 0
+    assert SHAPES[1][0] // 32 // 4 == 2 and SHAPES[1][0] // 64 == 4
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda s: "%dx%dx%d" % s)
+def run(request):
+    NX, NY, FRAMES = request.param
+    print(f"closure shapes {NX}x{NY}, {FRAMES} frames", flush=True)
     posts = []
     for f in range(FRAMES):
         fields = inputs.kelvin_helmholtz(NX, NY, u0=0.04 + 0.02 * f, delta=4.0, theta=0.35,
@@ -56,7 +75,7 @@ def run():
     torch.cuda.synchronize()
     acts = {k: net.activation(k).double().cpu().numpy() for k in range(7)}
     return dict(params=params, pb=split_params(params.to(torch.bfloat16).float()), acts=acts,
-                grads=grads.double().cpu().numpy())
+                grads=grads.double().cpu().numpy(), frames=FRAMES)
 
 
 def _conv_ok(got, x, w, b, relu, store_bf16):
@@ -74,7 +93,7 @@ def test_forward_layers(run):
     (w1, _), (w2, _), (w3, _) = run["pb"]
     b1, b2, b3 = (p[l * 9248 + 9216:l * 9248 + 9216 + c].double().cpu().numpy()
                   for l, c in ((0, 32), (1, 32), (2, 25)))
-    for f in range(FRAMES):
+    for f in range(run["frames"]):
         for got, x, w, b, relu, bf in ((a[1][f], a[0][f][..., :25], w1, b1, True, True),
                                        (a[2][f], a[1][f], w2, b2, True, True),
                                        (a[3][f][..., :25], a[2][f], w3, b3, False, False)):
@@ -90,7 +109,7 @@ def test_backward_layers(run):
              (a[0][..., :25], w1, a[6], None, 0, None)]
     for x, w, dz, act_below, layer, dz_below in chain:
         dw_ref, db_ref, dw_abs = np.zeros(w.shape), np.zeros(w.shape[3]), np.zeros(w.shape)
-        for f in range(FRAMES):
+        for f in range(run["frames"]):
             dx, dw, db = ocl.conv3x3_backward(x[f], w, dz[f])
             dabs = ocl.conv3x3_backward(np.abs(x[f]), np.abs(w), np.abs(dz[f]))
             dw_ref += dw

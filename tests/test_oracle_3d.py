@@ -110,3 +110,24 @@ def test_sound_speed_is_that_of_a_monatomic_gas():
     k = 2 * np.pi / L
     cs = np.sqrt(5.0 / 3.0 * th)
     assert abs(t0 / (np.pi / (2 * cs * k)) - 1) < 0.02
+
+
+def test_sums3_closed_form_on_equilibria():
+    """ref_sums3 against closed forms: on the equilibrium of random fields the
+    five-velocity rule reproduces the Maxwell moments to fourth order per axis,
+    so summed over the box
+        sum f = sum rho,  sum f v_a = sum rho u_a  (a = x, y, z),
+        sum f |v|^2 = sum rho (3 theta + |u|^2).
+    Independent, non-symmetric fields per axis make an exchanged weight (say
+    v_y for v_z) or a dropped term fail."""
+    shape = (4, 5, 6)
+    rho, ux, uy, uz, th = _fields(shape, 7, amp=0.08)
+    uy = uy + 0.03            # distinct mean momentum along each axis
+    uz = uz - 0.05
+    lat = oracle.Lattice3(6, 5, 4, omega=1.3)
+    s = lat.sums(lat.init(rho, ux, uy, uz, th))
+    ref = np.array([rho.sum(), (rho * ux).sum(), (rho * uy).sum(), (rho * uz).sum(),
+                    (rho * (3 * th + ux ** 2 + uy ** 2 + uz ** 2)).sum()])
+    assert np.abs(s - ref).max() < 1e-13 * np.abs(ref).max(), (s, ref)
+    # the momenta along the three axes differ, so an axis mix-up cannot pass
+    assert min(abs(ref[1] - ref[2]), abs(ref[2] - ref[3]), abs(ref[1] - ref[3])) > 0.1
