@@ -127,6 +127,8 @@ struct KParams {
 struct StF64 {
     using T = double;
     using C = double;
+    // per-node key of the stochastic rounding (unused by the other forms)
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
     static __device__ __forceinline__ C dec(T h, int, const KParams &) { return h; }
     static __device__ __forceinline__ T enc(C f, int, const KParams &, uint32_t = 0) { return f; }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r64; }
@@ -135,6 +137,8 @@ struct StF64 {
 struct StF32 {
     using T = float;
     using C = float;
+    // per-node key of the stochastic rounding (unused by the other forms)
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
     static __device__ __forceinline__ C dec(T h, int, const KParams &) { return h; }
     static __device__ __forceinline__ T enc(C f, int, const KParams &, uint32_t = 0) { return f; }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r32; }
@@ -147,6 +151,8 @@ struct StF32 {
 struct StF16 {
     using T = uint16_t;
     using C = float;
+    // per-node key of the stochastic rounding (unused by the other forms)
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
     static __device__ __forceinline__ C dec(T h, int k, const KParams &p) {
         const int c = pclass(k);
         return fmaf((float)__builtin_bit_cast(_Float16, h), p.dscale[c], p.dbase[c]);
@@ -161,6 +167,8 @@ struct StF16 {
 struct StBF16 {
     using T = uint16_t;
     using C = float;
+    // per-node key of the stochastic rounding (unused by the other forms)
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
     static __device__ __forceinline__ C dec(T h, int k, const KParams &p) {
         const int c = pclass(k);
         return fmaf(__uint_as_float((uint32_t)h << 16), p.dscale[c], p.dbase[c]);
@@ -178,48 +186,69 @@ struct StBF16 {
 // stored value is unbiased.  Round to nearest loses every per-step change
 // smaller than half an ulp of the deviation (2^-11 of it in FP16, 2^-8 in
 // BF16): a slowly decaying wave then decays at the wrong rate or not at all.
-// The random bits are a hash of the node, the population and the value's own
+// The random bits depend on the node, the population and the value's own
 // bits, so results are deterministic and independent of how the steps are
 // split into calls.
-__device__ __forceinline__ uint32_t sr_bits(uint32_t salt, int k, uint32_t vbits)
+//  - per node, once: a 32-bit key from the node index (two multiply-xorshift
+//    rounds, the finaliser of MurmurHash3);
+//  - per population: the low 24 bits of the value's bits xor the key, times
+//    a 24-bit odd constant of its own population (one full-rate 24 x 24
+//    multiply, low 32 bits kept); bits 16-31 of that product depend on all
+//    24 input bits and serve as 16 random bits (the top 13 for FP16).  An
+//    odd multiplier permutes the residues, so for a fixed value and a key
+//    uniform over the nodes the random bits are uniform: the rounding stays
+//    unbiased.  (The high half of the 48-bit product would not do: it only
+//    spans [0, multiplier / 2^8).)
+__device__ __forceinline__ uint32_t sr_node_key(uint32_t node)
 {
-    // the node term is the same for all 25 populations; per population a
-    // fold (the low 24 bits then carry every input bit) and a full-rate
-    // 24-bit multiply (a 32-bit one issues at a quarter of the rate), whose
-    // bits 16-31 depend on all 24: 16 random bits, 2-3 % faster overall
-    uint32_t h = salt * 0x85EBCA6Bu ^ (uint32_t)k * 0x632BE5ABu ^ vbits;
+    uint32_t h = node * 0x9E3779B1u;
     h ^= h >> 16;
-    return __umul24(h, 0x9E3779u) >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    return h;
 }
 
-// FP16: add 13 random bits below FP16's mantissa to the FP32 magnitude and
-// convert toward zero (one v_cvt_pkrtz).  Exact stochastic rounding in
-// FP16's normal range; below it (|h| < 2^-14, far under the deviations this
-// storage holds) the rounding is biased by less than 2^-25 scale.  |h| past
-// the FP16 range becomes infinity, as with round to nearest, so the sums
-// still report the overflow.
+__device__ __forceinline__ uint32_t sr_bits16(uint32_t key, int k, uint32_t vbits)
+{
+    // odd 24-bit multipliers, one per population (k < 25)
+    const uint32_t mult = 0x9E3779u + 0x2A62D6u * (uint32_t)k | 1u;
+    // (HIP's __umul24 returns int: shift the unsigned product, not the int)
+    return (uint32_t)__umul24(vbits ^ key, mult & 0xffffffu) >> 16;
+}
+
+// FP16: add 13 random bits below FP16's mantissa to the FP32 pattern, clear
+// those 13 bits, and convert (exactly, in FP16's normal range): the value
+// rounds up with probability equal to its distance from the lower FP16
+// neighbour.  Past the top of the range the sum reaches 65536 and converts
+// to infinity of v's sign (with the probability that makes the rounding
+// unbiased), so the sums still report the overflow; inf and NaN stay inf
+// and NaN (a NaN pattern cannot carry into the sign).  Below the FP16
+// normal range (|h| < 2^-14, far under the deviations this storage holds)
+// the truncated value rounds once more to the nearest subnormal.  No
+// branch: the random bits are computed for every population.
 struct StF16SR : StF16 {
-    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t salt) {
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return sr_node_key(node); }
+    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t key) {
         const int c = pclass(k);
         const float v = fmaf(f, p.dinv[c], p.dnbi[c]);
         const uint32_t vb = __float_as_uint(v);
-        const float vr = __uint_as_float(vb + (sr_bits(salt, k, vb) & 0x1fffu));
-        const uint16_t b = __builtin_bit_cast(uint16_t, __builtin_amdgcn_cvt_pkrtz(vr, 0.0f)[0]);
-        // past the FP16 range (or NaN): infinity of v's sign
-        return fabsf(v) < 65520.f ? b : (uint16_t)(((vb >> 16) & 0x8000u) | 0x7c00u);
+        const uint32_t t = (vb + (sr_bits16(key, k, vb) >> 3)) & ~0x1fffu;
+        return __builtin_bit_cast(uint16_t, (_Float16)__uint_as_float(t));
     }
 };
 
+// BF16 keeps FP32's upper 16 bits: adding 16 random bits to the pattern and
+// truncating rounds up with probability frac(v / ulp).  inf and NaN must
+// not move (a NaN pattern near all ones could carry into the sign): their
+// random bits are masked to zero, without a branch.
 struct StBF16SR : StBF16 {
-    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t salt) {
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return sr_node_key(node); }
+    static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t key) {
         const int c = pclass(k);
         const float v = fmaf(f, p.dinv[c], p.dnbi[c]);
         const uint32_t vb = __float_as_uint(v);
-        if ((vb & 0x7f800000u) == 0x7f800000u) return (uint16_t)(vb >> 16);   // inf / NaN
-        // BF16 keeps FP32's upper 16 bits: adding 16 random bits to the
-        // magnitude and truncating rounds up with probability frac(v / ulp)
-        const uint32_t r = sr_bits(salt, k, vb) & 0xffffu;
-        return (uint16_t)((vb + r) >> 16);
+        const uint32_t finite = (vb & 0x7f800000u) != 0x7f800000u ? 0xffffu : 0u;
+        return (uint16_t)((vb + (sr_bits16(key, k, vb) & finite)) >> 16);
     }
 };
 
@@ -289,6 +318,12 @@ __device__ __forceinline__ void rule1d(typename S::C u, typename S::C theta, con
     rule_sym<typename S::C>(u, theta, S::R(p), r);
 }
 
+// 1 / rho: correctly rounded in FP64; in FP32 the hardware reciprocal
+// (within 1 ulp), one instruction instead of a ten-instruction division, in
+// a step whose FP32 arithmetic already rounds each moment by several ulps.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // In place: f <- (1 - omega) f + omega f_eq (Eq. srt, collision half), with
 // f_eq = rho r^x_i r^y_j (tensor product, Eq. eqdist).
 template <class S>
@@ -297,7 +332,7 @@ __device__ __forceinline__ void collide2d(typename S::C (&f)[NQ], const KParams 
     using C = typename S::C;
     C rho, jx, jy, e;
     sums2d<S>(f, p, rho, jx, jy, e);
-    const C inv = C(1) / rho;
+    const C inv = recip(rho);
     const C ux = jx * inv, uy = jy * inv;
     const C theta = C(0.5) * (e * inv - ux * ux - uy * uy);
     C rx[Q], ry[Q];
@@ -546,20 +581,32 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
     // wave takes the vector path and only waves past the ragged right edge
     // mask their stores.
     unsigned lo[Q], so[Q];
+    // unsigned arithmetic: with nx up to 2^26 the FP64 offsets pass 2^31
+    const unsigned x0 = (unsigned)xb * (unsigned)sizeof(T);
+    if (NV == 1 && fast) {
+        // interior waves (all but the two at the seam): no lane wraps, so
+        // each offset is the lane's own plus a wave-uniform constant
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            lo[i] = x0 + (unsigned)(i * nx - p.sx[i]) * (unsigned)sizeof(T);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int xs;
+            if constexpr (NV == 1) {
+                xs = min(xb, nx - 1) - p.sx[i];
+                xs += (xs < 0) ? nx : 0;
+                xs -= (xs >= nx) ? nx : 0;
+                xs *= (int)sizeof(T);
+            } else {
+                xs = L::load_off(xb, p.sx[i]);
+            }
+            lo[i] = (unsigned)xs + (unsigned)i * (unsigned)nx * (unsigned)sizeof(T);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        int xs;
-        if constexpr (NV == 1) {
-            xs = min(xb, nx - 1) - p.sx[i];
-            xs += (xs < 0) ? nx : 0;
-            xs -= (xs >= nx) ? nx : 0;
-            xs *= (int)sizeof(T);
-        } else {
-            xs = L::load_off(xb, p.sx[i]);
-        }
-        // unsigned arithmetic: with nx up to 2^26 the FP64 offsets pass 2^31
-        lo[i] = (unsigned)xs + (unsigned)i * (unsigned)nx * (unsigned)sizeof(T);
-        so[i] = ((unsigned)xb + (unsigned)i * (unsigned)nx) * (unsigned)sizeof(T);
+        so[i] = x0 + (unsigned)i * (unsigned)nx * (unsigned)sizeof(T);
         asm volatile("" : "+v"(lo[i]), "+v"(so[i]));
     }
     const bool full = NV == 1 ? (wx + 64 <= nx) : fast;
@@ -621,7 +668,7 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
 #pragma unroll
             for (int k = 0; k < NQ; ++k) f[k] = S::dec(L::get(raw[k], m), k, p);
             collide2d<S>(f, p);
-            const uint32_t salt = (uint32_t)y * (uint32_t)nx + (uint32_t)(xb + m);   // the node
+            const uint32_t salt = S::key((uint32_t)y * (uint32_t)nx + (uint32_t)(xb + m));   // the node
 #pragma unroll
             for (int k = 0; k < NQ; ++k) out[k][m] = S::enc(f[k], k, p, salt);
             if constexpr (SUMS) {

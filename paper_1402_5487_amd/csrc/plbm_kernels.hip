@@ -120,7 +120,7 @@ __global__ __launch_bounds__(TX) void k_init2d(const double *__restrict__ rho,
                 xd -= (xd >= p.nx) ? p.nx : 0;
                 const int k = i + Q * j;
                 dst[k * p.pstride + (long long)yd * p.rstride + xd] =
-                    S::enc((typename S::C)feq[k], k, p, (uint32_t)n);
+                    S::enc((typename S::C)feq[k], k, p, S::key((uint32_t)n));
             }
         }
     }
