@@ -459,13 +459,84 @@ int plbm_closure_adam(plbm_closure *c, float *params, const float *grads, float 
 int plbm_closure_apply(plbm_closure *c, void *const *post, int frames, float bound,
                        unsigned *skipped, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Training the closure through several coarse steps: reverse-mode
+ * derivatives (vector-Jacobian products) of the step, of the apply and of a
+ * loss on the rolled-out state.  An adjoint buffer holds dL/dP for a
+ * population buffer P: FP64, the population layout of dim 2
+ * ((y * 25 + k) * nx + x), caller-owned device memory.  With Phi_k =
+ * (1, v_x, v_y, |v|^2), m = Phi^T f the conserved densities (rho, j_x, j_y,
+ * E = sum f |v|^2) and F(m) the equilibrium of Eq. eqdist (r = C mu of
+ * Eq. rdr at rho, u = j / rho, 2 theta = E / rho - |u|^2):
+ * ------------------------------------------------------------------------ */
+
+/*
+ * plbm_step_vjp -- adjoint of one step of Eq. srt on the buffer convention:
+ * for P' = (1 - omega) S + omega F(m(S)), S = pull(post),
+ *   out = dL/dpost = push((1 - omega) lam + omega Phi J_F(m)^T lam),
+ * with J_F the Jacobian of F (its derivatives from those of the Maxwell
+ * moments, d mu_n/du = n mu_(n-1), d mu_n/dtheta = n (n-1)/2 mu_(n-2)).
+ *   post : device, the buffer the step read (FP64 or FP32 storage)
+ *   lam  : device FP64 adjoint buffer, dL/dP' of the buffer the step wrote
+ *   out  : device FP64 adjoint buffer (written; must not alias lam)
+ * D2Q25 (symmetric five-velocity set, dim 2, ny <= 65535) only; other
+ * descriptors return PLBM_EUNSUPPORTED.  Asynchronous.
+ */
+int plbm_step_vjp(const plbm_desc *d, const void *post, const double *lam, double *out,
+                  void *stream);
+
+/*
+ * plbm_closure_rollout_loss -- loss of rolled-out states against the truth
+ *   L = scale sum_frames sum_x sum_j w_j (m_j(pull(post))(x) - cons_j(R)(x))^2
+ * with w_j = 1 / sigma_j^2 from plbm_closure_set_norm's moment_scale and
+ * cons(R) = (rho, rho u_x, rho u_y, rho (2 theta + |u|^2)) of the truth.
+ *   post  : host array of `frames` device population buffers (the states)
+ *   truth : host array of 4 * frames device FP64 planes (nx * ny each),
+ *           (rho, u_x, u_y, theta) of frame 0, then frame 1, ...
+ *   scale : > 0 (e.g. 1 / (steps * frames * nodes))
+ *   lam   : NULL, or host array of `frames` FP64 adjoint buffers to which
+ *           dL/dpost = push(Phi 2 scale w r) is added
+ *   loss  : NULL, or a host double receiving L (synchronises `stream`;
+ *           PLBM_ENONFINITE if not finite)
+ */
+int plbm_closure_rollout_loss(plbm_closure *c, void *const *post, const double *const *truth,
+                              int frames, double scale, double *const *lam, double *loss,
+                              void *stream);
+
+/*
+ * plbm_closure_apply_vjp -- adjoint of plbm_closure_apply (without its
+ * fallback bound) for the buffers the last plbm_closure_forward read.  With
+ * lam = dL/dpost' on entry (updated in place) and Lam = pull(lam):
+ *   lam <- lam + push(Phi (J_F(m + g) - J_F(m))^T Lam)    (the state path)
+ * and dL/dg = J_F(m + g)^T Lam is kept for plbm_closure_backward_vjp.  Nodes
+ * the apply would leave unshifted pass nothing.
+ *   post : the pre-apply buffers (as given to plbm_closure_forward)
+ *   lam  : host array of `frames` FP64 adjoint buffers
+ */
+int plbm_closure_apply_vjp(plbm_closure *c, void *const *post, double *const *lam, int frames,
+                           void *stream);
+
+/*
+ * plbm_closure_backward_vjp -- the network's part of the apply adjoint:
+ * from dL/dg of the last plbm_closure_apply_vjp, dL/dy = Ph (s * dL/dc)
+ * (plus the minimum-norm term reg), back through the three layers: the
+ * parameter gradient is written to `grads` (device, PLBM_CNN_PARAMS floats)
+ * or added to it when `accumulate` is non-zero, and, when lam is not NULL,
+ * the gradient of the network input is added to the adjoint buffers
+ * (lam += dL/dpost through the normalised input).  Asynchronous.
+ */
+int plbm_closure_backward_vjp(plbm_closure *c, const float *params, float reg, float *grads,
+                              int accumulate, double *const *lam, void *stream);
+
 /* Device pointer and size of an internal buffer (for tests):
  * 0 input, 1 layer-1 output, 2 layer-2 output (bf16 NHWC x 32), 3 network
  * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs,
  * 7 the physical correction c (FP32 planes [frame][k][y][x]),
  * 8 dL/dm (FP32 [frame][y][x][j], j = mass, x and y momentum, energy),
  * 9 the equilibrium shift of the last apply (FP64 planes [frame][k][y][x],
- * population k of node x). */
+ * population k of node x), 10 per-node moment cotangents of the last
+ * adjoint call (FP64 [frame][y][x][j]), 11 the gradient of the network
+ * input (FP32 NHWC x 32). */
 int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes);
 
 /*

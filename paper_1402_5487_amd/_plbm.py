@@ -239,6 +239,13 @@ def dev_scales(d, rho, ux, uy, theta, stream):
                               _ptr(theta), _stream(stream)), "plbm_dev_scales")
 
 
+def step_vjp(d, post, lam, out, stream):
+    """plbm_step_vjp: out = dL/dpost for the step that read `post`, given
+    lam = dL/d(the buffer it wrote) (FP64 adjoint buffers)."""
+    check(lib.plbm_step_vjp(ctypes.byref(d), _ptr(post), _ptr(lam), _ptr(out), _stream(stream)),
+          "plbm_step_vjp")
+
+
 def stream_copy(src, dst, nbytes, stream):
     """plbm_stream_copy: the HBM calibration copy."""
     check(lib.plbm_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)),
@@ -313,10 +320,18 @@ def _setup_closure(lib):
     lib.plbm_restrict.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   vp, vp, vp, vp, vp]
     lib.plbm_closure_target.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, vp, vp]
+    D = ctypes.POINTER(ctypes.c_double)
+    lib.plbm_step_vjp.argtypes = [P, vp, vp, vp, vp]
+    lib.plbm_closure_rollout_loss.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int,
+                                              ctypes.c_double, ctypes.POINTER(vp), D, vp]
+    lib.plbm_closure_apply_vjp.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.plbm_closure_backward_vjp.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int,
+                                              ctypes.POINTER(vp), vp]
 
 
 _setup_closure(lib)
 EXPORTED = EXPORTED + ("plbm_closure_create", "plbm_closure_destroy", "plbm_closure_set_norm",
                        "plbm_closure_forward", "plbm_closure_backward", "plbm_closure_adam",
                        "plbm_closure_apply", "plbm_closure_activation", "plbm_closure_target",
-                       "plbm_restrict")
+                       "plbm_restrict", "plbm_step_vjp", "plbm_closure_rollout_loss",
+                       "plbm_closure_apply_vjp", "plbm_closure_backward_vjp")

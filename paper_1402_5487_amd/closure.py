@@ -112,18 +112,47 @@ class Closure:
             None if skipped is None else ctypes.c_void_p(skipped.data_ptr()),
             _stream(self.device)), "plbm_closure_apply")
 
+    # -- training through coarse steps (adjoints) ---------------------------
+    def rollout_loss(self, posts, truths, scale, lams=None, want_loss=True):
+        """L = scale sum w_j (m_j - cons_j(truth))^2 over the states `posts`;
+        truths: per frame a (rho, ux, uy, theta) tuple of FP64 device fields;
+        lams: None or per-frame FP64 adjoint buffers receiving dL/dpost."""
+        flat = [t for tr in truths for t in tr]
+        loss = ctypes.c_double() if want_loss else None
+        _plbm.check(_plbm.lib.plbm_closure_rollout_loss(
+            self.handle, _ptrs(posts), _ptrs(flat), len(posts), float(scale),
+            None if lams is None else _ptrs(lams), ctypes.byref(loss) if want_loss else None,
+            _stream(self.device)), "plbm_closure_rollout_loss")
+        return loss.value if want_loss else None
+
+    def apply_vjp(self, posts, lams):
+        """Adjoint of apply for the buffers of the last forward (pre-apply);
+        lams (dL/dpost') are updated in place through the state path."""
+        _plbm.check(_plbm.lib.plbm_closure_apply_vjp(self.handle, _ptrs(posts), _ptrs(lams), len(posts),
+                                                     _stream(self.device)), "plbm_closure_apply_vjp")
+
+    def backward_vjp(self, params, grads, accumulate=True, lams=None, reg=0.0):
+        """The network's part of the apply adjoint: parameter gradients into
+        grads (added when accumulate) and, with lams, the input gradient."""
+        _plbm.check(_plbm.lib.plbm_closure_backward_vjp(
+            self.handle, ctypes.c_void_p(params.data_ptr()), float(reg), ctypes.c_void_p(grads.data_ptr()),
+            1 if accumulate else 0, None if lams is None else _ptrs(lams), _stream(self.device)),
+            "plbm_closure_backward_vjp")
+
     def activation(self, which):
         """Copy of an internal buffer: bf16 NHWC (which 0..2, 4..6) as float32
         (frames, ny, nx, 32), the FP32 output (3), the physical correction
-        (7: frames, 25, ny, nx), dL/dm (8: frames, 4, ny, nx) or the last
-        equilibrium shift (9: frames, 25, ny, nx)."""
+        (7: frames, 25, ny, nx), dL/dm (8: frames, 4, ny, nx), the last
+        equilibrium shift (9: frames, 25, ny, nx), the moment cotangents of the
+        last adjoint call (10: frames, 4, ny, nx) or the gradient of the
+        network input (11: frames, ny, nx, 32)."""
         ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
         _plbm.check(_plbm.lib.plbm_closure_activation(self.handle, int(which), ctypes.byref(ptr),
                                                       ctypes.byref(nbytes)), "activation")
         nodes = self.frames * self.ny * self.nx
-        if which == 9:
+        if which in (9, 10):
             out = torch.empty(nbytes.value // 8, dtype=torch.float64, device=self.device)
-        elif which in (3, 7, 8):
+        elif which in (3, 7, 8, 11):
             out = torch.empty(nbytes.value // 4, dtype=torch.float32, device=self.device)
         else:
             out = torch.empty(nodes * CH, dtype=torch.bfloat16, device=self.device)
@@ -132,8 +161,10 @@ class Closure:
         nf = max(self._nf, 1)
         if which in (7, 9):
             return out.reshape(self.frames, 25, self.ny, self.nx)[:nf]
-        if which == 8:
+        if which in (8, 10):
             return out.reshape(self.frames, self.ny, self.nx, 4).permute(0, 3, 1, 2)[:nf]
+        if which == 11:
+            return out.reshape(self.frames, self.ny, self.nx, CH)[:nf]
         return out.float().reshape(self.frames, self.ny, self.nx, CH)[:nf]
 
 

@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, 
 // MODE 0: forward hidden layer  out = bf16(relu(conv + bias))
 // MODE 1: forward last layer    out = f32(conv + bias)
 // MODE 2: input gradient        out = bf16(conv_mirrored(dz, W^T) * (act > 0))
+// MODE 3: network-input gradient out = f32(conv_mirrored(dz, W^T))  (no ReLU below)
 // ---------------------------------------------------------------------------
 // A block covers 4 waves x 32 nodes of `rows` consecutive rows; each lane
 // keeps its 18 weight operands in registers across the rows (the weights
@@ -206,7 +207,7 @@ __device__ __forceinline__ void cl_conv_row(bf16x8 (&A)[3][3][2], const bf16x8 (
         for (int d = 0; d < 3; ++d) {             // input column x - 1 + d
             // tap (ty, tx) of the kernel: the forward pass reads input y + ty - 1,
             // the input gradient (mirrored kernel) input y - ty + 1
-            const int t = (MODE == 2) ? (2 - r) * 3 + (2 - d) : r * 3 + d;
+            const int t = (MODE >= 2) ? (2 - r) * 3 + (2 - d) : r * 3 + d;
 #pragma unroll
             for (int h = 0; h < 2; ++h)
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[(P + r) % 3][d][h], bw[t][h], acc, 0, 0, 0);
@@ -221,7 +222,7 @@ __device__ __forceinline__ void cl_conv_row(bf16x8 (&A)[3][3][2], const bf16x8 (
         float v = acc[r] + bj;
         if (MODE == 0) {
             reinterpret_cast<u16 *>(out)[node * CH + j] = bf16_bits(fmaxf(v, 0.f));
-        } else if (MODE == 1) {
+        } else if (MODE == 1 || MODE == 3) {
             reinterpret_cast<float *>(out)[node * CH + j] = v;
         } else {
             const float a = bf16_val(act[node * CH + j]);
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(256, PLBM_CONV_WAVES) void k_cl_conv(const u16 *__r
 #pragma unroll
         for (int h = 0; h < 2; ++h)
             bw[t][h] = *reinterpret_cast<const bf16x8 *>(wb + ((size_t)t * CH + (l & 31)) * CH + h * 16 + 8 * kh);
-    const float bj = (MODE == 2) ? 0.f : bias[l & 31];
+    const float bj = (MODE >= 2) ? 0.f : bias[l & 31];
     int xs[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -457,14 +458,14 @@ __global__ __launch_bounds__(256) void k_cl_wgrad_slices(const float *__restrict
 }
 
 __global__ __launch_bounds__(256) void k_cl_wgrad_reduce(const float *__restrict__ slices,
-                                                         float *__restrict__ grad)
+                                                         float *__restrict__ grad, int accumulate)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= LAYER_P) return;
     float s = 0.f;
 #pragma unroll 8
     for (int z = 0; z < WR_SLICES; ++z) s += slices[(size_t)z * LAYER_P + i];
-    grad[i] = s;
+    grad[i] = accumulate ? grad[i] + s : s;
 }
 
 // ---------------------------------------------------------------------------
@@ -725,6 +726,255 @@ __global__ __launch_bounds__(256) void k_cl_scatter(PtrList post, const double *
     }
 }
 
+// ---------------------------------------------------------------------------
+// Training through coarse steps: adjoints (vector-Jacobian products, FP64).
+// With Phi_k = (1, v_x, v_y, |v|^2), m = Phi^T f the conserved densities
+// (rho, j_x, j_y, E) and F(m) the tensor-product equilibrium (Eq. eqdist with
+// r = C mu of Eq. rdr; rho, u = j / rho, 2 theta = E / rho - |u|^2):
+//   step   P' = (1 - w) S + w F(m(S)),  S = pull(P)
+//          dL/dP = push((1 - w) lam + w Phi J_F(m)^T lam)
+//   shift  P' = P + push(F(m + g) - F(m)),  m = m(pull(P)),
+//          g = Phi^T (pull(c) - c)
+//          dL/dP = lam + push(Phi (J_F(m + g) - J_F(m))^T Lam),
+//          dL/dg = J_F(m + g)^T Lam,  Lam = pull(lam)
+//   loss   L = scale sum_x sum_j w_j (m_j(pull(P))(x) - cons_j(R)(x))^2
+//          dL/dP = push(Phi a),  a = 2 scale w r
+// Adjoint buffers have the population layout (y * 25 + k) * nx + x in FP64.
+// ---------------------------------------------------------------------------
+
+// r, dr/du and dr/dtheta of the symmetric 1D rule: the Maxwell moments and
+// their derivatives d mu_n/du = n mu_(n-1), d mu_n/dtheta = n (n-1)/2 mu_(n-2)
+// go through the same linear map r = C mu (without its constant for the
+// derivatives).
+__device__ __forceinline__ void rule_lin(const SymRule<double> &R, double m1, double m2, double m3, double m4,
+                                         double c0, double (&r)[Q])
+{
+    const double e1 = R.c12 * m2 + R.c14 * m4, o1 = R.c11 * m1 + R.c13 * m3;
+    const double e3 = R.c32 * m2 + R.c34 * m4, o3 = R.c31 * m1 + R.c33 * m3;
+    r[0] = c0 + R.c02 * m2 + R.c04 * m4;
+    r[1] = e1 + o1;
+    r[2] = e1 - o1;
+    r[3] = e3 + o3;
+    r[4] = e3 - o3;
+}
+
+__device__ __forceinline__ void rule_derivs(const SymRule<double> &R, double u, double th, double (&r)[Q],
+                                            double (&ru)[Q], double (&rt)[Q])
+{
+    const double m2 = u * u + th, m3 = u * m2 + 2.0 * th * u, m4 = u * m3 + 3.0 * th * m2;
+    rule_lin(R, u, m2, m3, m4, 1.0, r);
+    rule_lin(R, 1.0, 2.0 * u, 3.0 * m2, 4.0 * m3, 0.0, ru);
+    rule_lin(R, 0.0, 1.0, 3.0 * u, 6.0 * m2, 0.0, rt);
+}
+
+// a = J_F(m)^T lam for conserved densities m and cotangents lam[k = i + 5 j]
+__device__ __forceinline__ void feq_vjp(const SymRule<double> &R, const double (&m)[4], const double (&lam)[NQ],
+                                        double (&a)[4])
+{
+    const double rho = m[0], inv = 1.0 / rho;
+    const double ux = m[1] * inv, uy = m[2] * inv;
+    const double th = 0.5 * (m[3] * inv - ux * ux - uy * uy);
+    double rx[Q], rxu[Q], rxt[Q], ry[Q], ryu[Q], ryt[Q];
+    rule_derivs(R, ux, th, rx, rxu, rxt);
+    rule_derivs(R, uy, th, ry, ryu, ryt);
+    double gr = 0.0, gu = 0.0, gw = 0.0, gt = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        double lr = 0.0, lu = 0.0, lt = 0.0;        // sum over i of lam_ij (r_i, r'_i, rdot_i)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double l = lam[i + Q * j];
+            lr += l * rx[i];
+            lu += l * rxu[i];
+            lt += l * rxt[i];
+        }
+        gr += ry[j] * lr;
+        gu += ry[j] * lu;
+        gw += ryu[j] * lr;
+        gt += ry[j] * lt + ryt[j] * lr;
+    }
+    gu *= rho;
+    gw *= rho;
+    gt *= rho;
+    a[0] = gr - (gu * ux + gw * uy) * inv + 0.5 * gt * (ux * ux + uy * uy - 2.0 * th) * inv;
+    a[1] = (gu - gt * ux) * inv;
+    a[2] = (gw - gt * uy) * inv;
+    a[3] = 0.5 * gt * inv;
+}
+
+__device__ __forceinline__ int wrap(int i, int n)
+{
+    i += i < 0 ? n : 0;
+    return i - (i >= n ? n : 0);
+}
+
+// Step adjoint, one node per thread: from lam = dL/dP' at node x and the
+// conserved densities of S(x) = pull(P)(x), mu = (1 - w) lam + w Phi J^T lam,
+// scattered to dL/dP(x - v_k)_k = mu_k (each target written exactly once).
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_vjp(const T *__restrict__ P, const double *__restrict__ lam,
+                                                  double *__restrict__ out, int nx, int ny, KParams kp)
+{
+    const int y = blockIdx.y, x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    double m[4] = {0.0, 0.0, 0.0, 0.0}, l[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int vx = kp.sx[k % Q], vy = kp.sx[k / Q];
+        const double f = (double)P[((size_t)wrap(y - vy, ny) * NQ + k) * nx + wrap(x - vx, nx)];
+        m[0] += f;
+        m[1] += vx * f;
+        m[2] += vy * f;
+        m[3] += (vx * vx + vy * vy) * f;
+        l[k] = lam[((size_t)y * NQ + k) * nx + x];
+    }
+    double a[4];
+    feq_vjp(kp.r64, m, l, a);
+    const double w = kp.r64.omega;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int vx = kp.sx[k % Q], vy = kp.sx[k / Q];
+        const double phi_a = a[0] + vx * a[1] + vy * a[2] + (vx * vx + vy * vy) * a[3];
+        out[((size_t)wrap(y - vy, ny) * NQ + k) * nx + wrap(x - vx, nx)] = (1.0 - w) * l[k] + w * phi_a;
+    }
+}
+
+// Up to MAX_FRAMES sets of (rho, u_x, u_y, theta) planes.
+struct TruthList {
+    const double *p[4 * MAX_FRAMES];
+};
+
+// Rollout loss at one step: residual r = m(pull(P)) - cons(R) per node and
+// moment, a = 2 scale w r (double4 per node), loss partials scale w r^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_rloss(PtrList post, TruthList truth, int nx, int ny, ClNorm nm,
+                                                  double scale, double *__restrict__ A,
+                                                  double *__restrict__ lpart)
+{
+    __shared__ double red[4];
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    double lsum = 0.0;
+    if (x < nx) {
+        const T *P = static_cast<const T *>(post.p[f]);
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < CREAL; ++k) {
+            const double v = (double)P[((size_t)wrap(y - nm.ivy[k], ny) * CREAL + k) * nx +
+                                       wrap(x - nm.ivx[k], nx)];
+            const double vx = nm.ivx[k], vy = nm.ivy[k];
+            m[0] += v;
+            m[1] += vx * v;
+            m[2] += vy * v;
+            m[3] += (vx * vx + vy * vy) * v;
+        }
+        const size_t at = (size_t)y * nx + x;
+        const double r0 = truth.p[4 * f][at], u = truth.p[4 * f + 1][at], w = truth.p[4 * f + 2][at],
+                     t = truth.p[4 * f + 3][at];
+        const double c[4] = {r0, r0 * u, r0 * w, r0 * (2.0 * t + u * u + w * w)};
+        double a[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double r = m[j] - c[j];
+            lsum += scale * (double)nm.mw2[j] * r * r;
+            a[j] = 2.0 * scale * (double)nm.mw2[j] * r;
+        }
+        double *dst = A + ((size_t)f * ny * nx + at) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[j] = a[j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        lpart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
+            (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// lam(y)_k += Phi_k . a(y + v_k): the push of per-node moment cotangents
+__global__ __launch_bounds__(256) void k_cl_push4(const double *__restrict__ A, PtrList lam, int nx, int ny,
+                                                  ClNorm nm)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    double *L = static_cast<double *>(lam.p[f]);
+    const double *Af = A + (size_t)f * ny * nx * 4;
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        const double *a = Af + ((size_t)wrap(y + nm.ivy[k], ny) * nx + wrap(x + nm.ivx[k], nx)) * 4;
+        const double vx = nm.ivx[k], vy = nm.ivy[k];
+        L[((size_t)y * CREAL + k) * nx + x] += a[0] + vx * a[1] + vy * a[2] + (vx * vx + vy * vy) * a[3];
+    }
+}
+
+// Shift adjoint, per node: Lam = pull(lam)(x), m from pull(P), g from c (as
+// k_cl_shift); writes a_g = J_F(m + g)^T Lam as the moment cotangent of the
+// correction (float4, read by k_cl_mgrad) and a_m = a_g - J_F(m)^T Lam
+// (double4, pushed into lam by k_cl_push4).  Nodes the forward left
+// unshifted (density or temperature not positive) pass nothing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_shift_vjp(PtrList post, PtrList lam, const float *__restrict__ C,
+                                                      int nx, int ny, ClNorm nm, KParams kp,
+                                                      float *__restrict__ Ag, double *__restrict__ Am)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const size_t plane = (size_t)nx * ny;
+    const T *P = static_cast<const T *>(post.p[f]);
+    const double *L = static_cast<const double *>(lam.p[f]);
+    double m[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0}, l[NQ];
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        const int xs = wrap(x - nm.ivx[k], nx), ys = wrap(y - nm.ivy[k], ny);
+        const double v = (double)P[((size_t)ys * CREAL + k) * nx + xs];
+        l[k] = L[((size_t)ys * CREAL + k) * nx + xs];
+        const float *ck = C + ((size_t)f * CREAL + k) * plane;
+        const double c = (double)ck[(size_t)ys * nx + xs] - (double)ck[(size_t)y * nx + x];
+        const double vx = nm.ivx[k], vy = nm.ivy[k], v2 = vx * vx + vy * vy;
+        m[0] += v;
+        m[1] += vx * v;
+        m[2] += vy * v;
+        m[3] += v2 * v;
+        g[0] += c;
+        g[1] += vx * c;
+        g[2] += vy * c;
+        g[3] += v2 * c;
+    }
+    double m1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m1[j] = m[j] + g[j];
+    const double ux1 = m1[1] / m1[0], uy1 = m1[2] / m1[0];
+    const double th1 = 0.5 * (m1[3] / m1[0] - ux1 * ux1 - uy1 * uy1);
+    const bool ok = m1[0] > 0.0 && th1 > 0.0 && isfinite(th1);
+    double ag[4] = {0.0, 0.0, 0.0, 0.0}, a0[4] = {0.0, 0.0, 0.0, 0.0};
+    if (ok) {
+        feq_vjp(kp.r64, m1, l, ag);
+        feq_vjp(kp.r64, m, l, a0);
+    }
+    const size_t node = (size_t)f * plane + (size_t)y * nx + x;
+    reinterpret_cast<float4 *>(Ag)[node] = make_float4((float)ag[0], (float)ag[1], (float)ag[2], (float)ag[3]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Am[node * 4 + j] = ag[j] - a0[j];
+}
+
+// The network input is the normalised post-collision buffer at the node
+// itself, x_k = (P_k - mean_k) * inv_k: lam(x)_k += inv_k dL/dx_k.
+__global__ __launch_bounds__(256) void k_cl_input_vjp(const float *__restrict__ dx, PtrList lam, int nx, int ny,
+                                                      ClNorm nm)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    double *L = static_cast<double *>(lam.p[f]);
+    const size_t node = ((size_t)f * ny + y) * nx + x;
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k)
+        L[((size_t)y * CREAL + k) * nx + x] += (double)nm.in_inv[k] * (double)dx[node * CH + k];
+}
+
 // FP32 parameters -> bf16 [t][o][i] (forward) and [t][i][o] (input gradient)
 __global__ __launch_bounds__(256) void k_cl_cast(const float *__restrict__ params, u16 *__restrict__ wf,
                                                  u16 *__restrict__ wt)
@@ -801,6 +1051,9 @@ struct plbm_closure {
     float *corr = nullptr;                     // c = s * Ph y, planes [f][k][y][x]
     float *mres = nullptr;                     // (2/N) w r, [f][y][x][j]
     double *shift = nullptr;                   // equilibrium shift, planes [f][k][y][x]
+    double *adj4 = nullptr;                    // per-node moment cotangents (adjoints), [f][y][x][j]
+    float *dx = nullptr;                       // gradient of the network input, NHWC x 32
+    double *lpart64 = nullptr;                 // rollout-loss partials
     KParams kp;                                // the coarse lattice's rule
     int nwblk = 0, nlblk = 0;
     int frames_in_fwd = 0;
@@ -851,11 +1104,42 @@ int make_list(PtrList &l, const P *host, int n)
     return PLBM_OK;
 }
 
-void reduce_wgrad(plbm_closure *c, int nwblk, float *grad, hipStream_t st)
+void reduce_wgrad(plbm_closure *c, int nwblk, float *grad, hipStream_t st, int accumulate = 0)
 {
     hipLaunchKernelGGL(k_cl_wgrad_slices, dim3((LAYER_P + 255) / 256, WR_SLICES), dim3(256), 0, st, c->part,
                        nwblk, c->slices);
-    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->slices, grad);
+    hipLaunchKernelGGL(k_cl_wgrad_reduce, dim3((LAYER_P + 255) / 256), dim3(256), 0, st, c->slices, grad,
+                       accumulate);
+}
+
+// From dy3 (the gradient of the network output): the weight gradients of the
+// three layers (written, or added to `grads` when accumulate), dz2 and dz1,
+// and with input_grad the gradient of the network input into c->dx.
+void layers_backward(plbm_closure *c, int frames, float *grads, int accumulate, hipStream_t st,
+                     bool input_grad = false)
+{
+    const int crows = conv_rows(c->nx, c->ny, frames);
+    // the input-gradient pass (with its ReLU mask read) is fastest at half the rows
+    const int brows = std::max(1, crows / PLBM_CONV_BROWS_DIV);
+    const dim3 gb((c->nx / 32 + 3) / 4, (c->ny + brows - 1) / brows, frames);
+    const dim3 gw((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS), 1, frames);
+    const int nwblk = (int)(gw.x * gw.z);
+    // layer 3: dW3 from a2 and dy3; dz2 = (W3^T dy3) * (a2 > 0)
+    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a2, c->dy3, c->nx, c->ny, c->part);
+    reduce_wgrad(c, nwblk, grads + 2 * LAYER_P, st, accumulate);
+    hipLaunchKernelGGL(k_cl_conv<2>, gb, dim3(256), 0, st, c->dy3, c->wt + 2 * LAYER_W, nullptr, c->a2,
+                       c->dz2, c->nx, c->ny, brows);
+    // layer 2
+    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a1, c->dz2, c->nx, c->ny, c->part);
+    reduce_wgrad(c, nwblk, grads + LAYER_P, st, accumulate);
+    hipLaunchKernelGGL(k_cl_conv<2>, gb, dim3(256), 0, st, c->dz2, c->wt + LAYER_W, nullptr, c->a1, c->dz1,
+                       c->nx, c->ny, brows);
+    // layer 1
+    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->x0, c->dz1, c->nx, c->ny, c->part);
+    reduce_wgrad(c, nwblk, grads, st, accumulate);
+    if (input_grad)
+        hipLaunchKernelGGL(k_cl_conv<3>, gb, dim3(256), 0, st, c->dz1, c->wt, nullptr, nullptr, c->dx, c->nx,
+                           c->ny, brows);
 }
 
 int cast_weights(plbm_closure *c, const float *params, hipStream_t st)
@@ -925,7 +1209,10 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
               hipMalloc((void **)&c->slices, (size_t)WR_SLICES * LAYER_P * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->corr, nodes * CREAL * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->mres, nodes * 4 * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&c->shift, nodes * CREAL * sizeof(double)) == hipSuccess;
+              hipMalloc((void **)&c->shift, nodes * CREAL * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&c->adj4, nodes * 4 * sizeof(double)) == hipSuccess &&
+              hipMalloc((void **)&c->dx, nodes * CH * sizeof(float)) == hipSuccess &&
+              hipMalloc((void **)&c->lpart64, (size_t)c->nlblk * sizeof(double)) == hipSuccess;
     if (!ok) {
         plbm_closure_destroy(c);
         return PLBM_EHIP;
@@ -939,7 +1226,7 @@ extern "C" int plbm_closure_destroy(plbm_closure *c)
     if (!c) return PLBM_EINVAL;
     (void)hipDeviceSynchronize();
     void *ptrs[] = {c->wf, c->wt, c->x0, c->a1, c->a2, c->y3, c->dy3, c->dz2, c->dz1, c->part,
-                    c->lpart, c->corr, c->mres, c->shift, c->slices};
+                    c->lpart, c->corr, c->mres, c->shift, c->slices, c->adj4, c->dx, c->lpart64};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -1015,32 +1302,13 @@ extern "C" int plbm_closure_backward(plbm_closure *c, const float *params, const
     if (rc != PLBM_OK) return rc;
     (void)hipGetLastError();
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
-    const int crows = conv_rows(c->nx, c->ny, frames);
-    const dim3 gc((c->nx / 32 + 3) / 4, (c->ny + crows - 1) / crows, frames);
-    // the input-gradient pass (with its ReLU mask read) is fastest at half the rows
-    const int brows = std::max(1, crows / PLBM_CONV_BROWS_DIV);
-    const dim3 gb((c->nx / 32 + 3) / 4, (c->ny + brows - 1) / brows, frames);
-    const dim3 gw((c->nx / WG_SEG) * ((c->ny + WG_ROWS - 1) / WG_ROWS), 1, frames);
-    const int nwblk = (int)(gw.x * gw.z);
     const float inv_n = 1.0f / ((float)frames * c->nx * c->ny);
     hipLaunchKernelGGL(k_cl_corr, gn, dim3(256), 0, st, c->y3, c->nx, c->ny, c->nm, reg, c->corr, c->lpart);
     hipLaunchKernelGGL(k_cl_mloss, gn, dim3(256), 0, st, c->corr, tl, c->nx, c->ny, c->nm, inv_n, c->mres,
                        c->lpart);
     hipLaunchKernelGGL(k_cl_mgrad, gn, dim3(256), 0, st, c->mres, c->y3, c->nx, c->ny, c->nm, 2.f * reg * inv_n,
                        c->dy3);
-    // layer 3: dW3 from a2 and dy3; dz2 = (W3^T dy3) * (a2 > 0)
-    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a2, c->dy3, c->nx, c->ny, c->part);
-    reduce_wgrad(c, nwblk, grads + 2 * LAYER_P, st);
-    hipLaunchKernelGGL(k_cl_conv<2>, gb, dim3(256), 0, st, c->dy3, c->wt + 2 * LAYER_W, nullptr, c->a2,
-                       c->dz2, c->nx, c->ny, brows);
-    // layer 2
-    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->a1, c->dz2, c->nx, c->ny, c->part);
-    reduce_wgrad(c, nwblk, grads + LAYER_P, st);
-    hipLaunchKernelGGL(k_cl_conv<2>, gb, dim3(256), 0, st, c->dz2, c->wt + LAYER_W, nullptr, c->a1, c->dz1,
-                       c->nx, c->ny, brows);
-    // layer 1
-    hipLaunchKernelGGL(k_cl_wgrad, gw, dim3(256), 0, st, c->x0, c->dz1, c->nx, c->ny, c->part);
-    reduce_wgrad(c, nwblk, grads, st);
+    layers_backward(c, frames, grads, 0, st);
     rc = ck(hipGetLastError());
     if (rc != PLBM_OK || !loss) return rc;
     const int nl = (int)(gn.x * gn.y * gn.z);
@@ -1090,6 +1358,117 @@ extern "C" int plbm_closure_apply(plbm_closure *c, void *const *post, int frames
     return ck(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Training through coarse steps (adjoints)
+// ---------------------------------------------------------------------------
+extern "C" int plbm_step_vjp(const plbm_desc *d, const void *post, const double *lam, double *out,
+                             void *stream)
+{
+    if (!d || d->dim != 2 || (d->storage != PLBM_F64 && d->storage != PLBM_F32)) return PLBM_EUNSUPPORTED;
+    if (plbm::gen_handles(d) || d->q1d != Q) return PLBM_EUNSUPPORTED;
+    KParams kp;
+    const int rc = make_params(d, kp);
+    if (rc != PLBM_OK) return rc;
+    if (!post || !lam || !out || lam == out || d->ny > 65535) return PLBM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const dim3 g((d->nx + 255) / 256, d->ny);
+    if (d->storage == PLBM_F64)
+        hipLaunchKernelGGL(k_step_vjp<double>, g, dim3(256), 0, st, static_cast<const double *>(post), lam, out,
+                           d->nx, d->ny, kp);
+    else
+        hipLaunchKernelGGL(k_step_vjp<float>, g, dim3(256), 0, st, static_cast<const float *>(post), lam, out,
+                           d->nx, d->ny, kp);
+    return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_rollout_loss(plbm_closure *c, void *const *post, const double *const *truth,
+                                         int frames, double scale, double *const *lam, double *loss,
+                                         void *stream)
+{
+    if (!c || !post || !truth || frames < 1 || frames > c->frames || !(scale > 0.0) || !std::isfinite(scale))
+        return PLBM_EINVAL;
+    PtrList pl, ll;
+    int rc = make_list(pl, post, frames);
+    if (rc != PLBM_OK) return rc;
+    if (lam) {
+        rc = make_list(ll, lam, frames);
+        if (rc != PLBM_OK) return rc;
+    }
+    TruthList tl;
+    for (int i = 0; i < 4 * frames; ++i) {
+        if (!truth[i]) return PLBM_EINVAL;
+        tl.p[i] = truth[i];
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    if (c->f64)
+        hipLaunchKernelGGL(k_cl_rloss<double>, gn, dim3(256), 0, st, pl, tl, c->nx, c->ny, c->nm, scale, c->adj4,
+                           c->lpart64);
+    else
+        hipLaunchKernelGGL(k_cl_rloss<float>, gn, dim3(256), 0, st, pl, tl, c->nx, c->ny, c->nm, scale, c->adj4,
+                           c->lpart64);
+    if (lam) hipLaunchKernelGGL(k_cl_push4, gn, dim3(256), 0, st, c->adj4, ll, c->nx, c->ny, c->nm);
+    rc = ck(hipGetLastError());
+    if (rc != PLBM_OK || !loss) return rc;
+    const int nl = (int)(gn.x * gn.y * gn.z);
+    std::vector<double> h(nl);
+    rc = ck(hipMemcpyAsync(h.data(), c->lpart64, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (rc == PLBM_OK) rc = ck(hipStreamSynchronize(st));
+    if (rc != PLBM_OK) return rc;
+    double sum = 0.0;
+    for (double v : h) sum += v;
+    *loss = sum;
+    return std::isfinite(sum) ? PLBM_OK : PLBM_ENONFINITE;
+}
+
+extern "C" int plbm_closure_apply_vjp(plbm_closure *c, void *const *post, double *const *lam, int frames,
+                                      void *stream)
+{
+    if (!c || !post || !lam || frames < 1 || frames != c->frames_in_fwd) return PLBM_EINVAL;
+    PtrList pl, ll;
+    int rc = make_list(pl, post, frames);
+    if (rc == PLBM_OK) rc = make_list(ll, lam, frames);
+    if (rc != PLBM_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    // the correction of the last forward pass, without the fallback bound
+    hipLaunchKernelGGL(k_cl_corr_apply, gn, dim3(256), 0, st, c->y3, c->nx, c->ny, c->nm, INFINITY, c->corr,
+                       nullptr);
+    if (c->f64)
+        hipLaunchKernelGGL(k_cl_shift_vjp<double>, gn, dim3(256), 0, st, pl, ll, c->corr, c->nx, c->ny, c->nm,
+                           c->kp, c->mres, c->adj4);
+    else
+        hipLaunchKernelGGL(k_cl_shift_vjp<float>, gn, dim3(256), 0, st, pl, ll, c->corr, c->nx, c->ny, c->nm,
+                           c->kp, c->mres, c->adj4);
+    hipLaunchKernelGGL(k_cl_push4, gn, dim3(256), 0, st, c->adj4, ll, c->nx, c->ny, c->nm);
+    return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_backward_vjp(plbm_closure *c, const float *params, float reg, float *grads,
+                                         int accumulate, double *const *lam, void *stream)
+{
+    if (!c || !params || !grads || c->frames_in_fwd < 1 || !(reg >= 0.f) || !std::isfinite(reg))
+        return PLBM_EINVAL;
+    const int frames = c->frames_in_fwd;
+    PtrList ll;
+    if (lam) {
+        const int rc = make_list(ll, lam, frames);
+        if (rc != PLBM_OK) return rc;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    const float inv_n = 1.0f / ((float)frames * c->nx * c->ny);
+    hipLaunchKernelGGL(k_cl_mgrad, gn, dim3(256), 0, st, c->mres, c->y3, c->nx, c->ny, c->nm, 2.f * reg * inv_n,
+                       c->dy3);
+    layers_backward(c, frames, grads, accumulate ? 1 : 0, st, lam != nullptr);
+    if (lam) hipLaunchKernelGGL(k_cl_input_vjp, gn, dim3(256), 0, st, c->dx, ll, c->nx, c->ny, c->nm);
+    return ck(hipGetLastError());
+}
+
 extern "C" int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes)
 {
     if (!c || !ptr) return PLBM_EINVAL;
@@ -1107,6 +1486,8 @@ extern "C" int plbm_closure_activation(const plbm_closure *c, int which, const v
     case 7: p = c->corr; b = nodes * CREAL * sizeof(float); break;
     case 8: p = c->mres; b = nodes * 4 * sizeof(float); break;
     case 9: p = c->shift; b = nodes * CREAL * sizeof(double); break;
+    case 10: p = c->adj4; b = nodes * 4 * sizeof(double); break;
+    case 11: p = c->dx; b = nodes * CH * sizeof(float); break;
     default: return PLBM_EINVAL;
     }
     *ptr = p;
