@@ -79,8 +79,11 @@ def parse():
                     help="steps of the batching form (0 skips it)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batching form (for profilers)")
-    ap.add_argument("--closure-iters", type=int, default=2000,
-                    help="training iterations of the learned closure (0 skips it)")
+    ap.add_argument("--closure-iters", type=int, default=600,
+                    help="training iterations (segments of 32 coarse steps x 8 runs) of the "
+                         "learned closure (0 skips it)")
+    ap.add_argument("--closure-storage", default="f32", choices=("f32", "f64"),
+                    help="populations of the coarse lattice the closure corrects")
     ap.add_argument("--closure-train-seeds", type=int, default=200)
     ap.add_argument("--closure-held-seeds", type=int, default=20)
     ap.add_argument("--q9-forms", default="q9f64,q9f32",
@@ -541,13 +544,15 @@ def predict_literal_batch(lb):
 
 
 def closure_form(args):
-    """Learned closure: coarse 256^2 KH (FP64 populations, omega viscosity-matched),
-    network trained on restricted 1024^2 runs of the training seeds, judged on
-    held-out seeds against the restricted fine run over 500 coarse steps."""
+    """Learned closure: coarse 256^2 KH (FP32 populations, omega viscosity-
+    matched), the network trained through coarse steps on the restricted
+    1024^2 runs of the training seeds, judged on held-out seeds against the
+    restricted fine run over 500 coarse steps (and judged again with FP64
+    coarse populations)."""
     from paper_1402_5487_amd import closure_train
     nt, nh = args.closure_train_seeds, args.closure_held_seeds
     return closure_train.run(train_seeds=range(nt), held_seeds=range(200, 200 + nh),
-                             iters=args.closure_iters, log=log)
+                             iters=args.closure_iters, storage=args.closure_storage, log=log)
 
 
 def cpu_baseline(n, fields, steps):

@@ -37,20 +37,27 @@ from .closure import Closure, init_params, restrict, target
 from .lattice import Lattice
 
 
+def _cons(fields):
+    """(rho, rho u_x, rho u_y, rho (2 theta + |u|^2)) stacked, (4, ny, nx)."""
+    r, u, w, t = fields
+    return torch.stack([r, r * u, r * w, r * (2.0 * t + u * u + w * w)])
+
+
 def coarse_omega(omega_f, factor):
     return 1.0 / (0.5 + (1.0 / omega_f - 0.5) / factor)
 
 
 class Experiment:
     def __init__(self, n_coarse=256, factor=4, theta=0.35, omega_f=1.8, device="cuda:0",
-                 batch=8, restart=25, reg=0.1):
+                 batch=8, restart=25, reg=0.1, storage="f64"):
         self.nc, self.factor = n_coarse, factor
         self.nf = n_coarse * factor
         self.theta, self.omega_f = theta, omega_f
         self.omega_c = coarse_omega(omega_f, factor)
         self.device = torch.device(device)
         self.batch, self.restart, self.reg = batch, restart, reg
-        self.net = Closure(self.nc, self.nc, batch, device, storage="f64")
+        self.storage = storage          # the coarse lattice's populations
+        self.net = Closure(self.nc, self.nc, batch, device, storage=storage)
         self.frames = []          # (post FP64 coarse buffer, d FP32 (4, n, n), steps since restart)
         self.params = None
         self.bound = 8.0
@@ -66,8 +73,9 @@ class Experiment:
         return Lattice(2, self.nf, self.nf, omega=self.omega_f, storage="f64",
                        device=self.device).init(*self.fine_fields(seed))
 
-    def coarse_lattice(self):
-        return Lattice(2, self.nc, self.nc, omega=self.omega_c, storage="f64", device=self.device)
+    def coarse_lattice(self, storage=None):
+        return Lattice(2, self.nc, self.nc, omega=self.omega_c, storage=storage or self.storage,
+                       device=self.device)
 
     def restricted(self, fine):
         return restrict(*fine.moments(), self.factor)
@@ -166,6 +174,24 @@ class Experiment:
         l0, l1 = self.loss_on(frames, zero), self.loss_on(frames)
         return l0, l1, 1.0 - l1 / l0
 
+    def calibrate_bound_rollout(self, seeds, steps=100, factor=4.0):
+        """Fallback bound from corrected rollouts of training seeds: `factor`
+        times the largest normalised projected correction |Ph y|_k the
+        trained network gives along them, so the fallback engages only on
+        states unlike those it was trained on."""
+        s = torch.tensor(self.norm[2], dtype=torch.float32, device=self.device).view(1, 25, 1, 1)
+        worst = 0.0
+        for seed in seeds:
+            fine = self.fine_lattice(seed)
+            corr = self.coarse_lattice().init(*self.restricted(fine))
+            for _ in range(steps):
+                corr.step(1)
+                self.net.forward(self.params, [corr.f])
+                self.net.apply([corr.f], bound=float("inf"))
+                worst = max(worst, float((self.net.activation(7)[:1] / s).abs().max()))
+        self.bound = factor * worst
+        return self.bound
+
     def calibrate_bound(self, frames, factor=4.0):
         """Fallback bound: `factor` times the largest normalised projected
         correction |Ph y|_k the trained network gives on `frames`, so the
@@ -181,15 +207,134 @@ class Experiment:
         self.bound = factor * worst
         return self.bound
 
+    # -- training through coarse steps ------------------------------------
+    def fit_rollout_scale(self, seeds, steps=50, emphasis=(1.0, 1.0, 1.0, 1.0)):
+        """Loss weights of rollout training: sigma_j = the rms over nodes and
+        steps of the plain coarse run's state error in each conserved density
+        (mass, the two momenta, energy) against the restricted fine run,
+        started from the equilibrium of R_0 as the judge starts."""
+        acc = torch.zeros(4, dtype=torch.float64, device=self.device)
+        n = 0
+        for seed in seeds:
+            fine = self.fine_lattice(seed)
+            coarse = self.coarse_lattice().init(*self.restricted(fine))
+            for _ in range(steps):
+                fine.step(self.factor)
+                coarse.step(1)
+                d = _cons(self.restricted(fine)) - _cons(coarse.moments())
+                acc += d.pow(2).mean(dim=(1, 2))
+                n += 1
+        sig = (acc / n).sqrt().clamp_min(1e-30)
+        # a moment with emphasis e weighs e times more (sigma / sqrt(e))
+        sig = sig / torch.tensor(emphasis, dtype=torch.float64, device=self.device).sqrt()
+        norm = list(self.norm)
+        norm[3] = sig.tolist()
+        self.norm = tuple(norm)
+        self.net.set_norm(*self.norm)
+        return sig.tolist()
+
+    def train_rollout(self, seeds, iters, seg=32, horizon=500, lr=2e-4, reg=0.0, seed=0,
+                      log=None):
+        """Adam on the rollout loss: `batch` corrected coarse runs, each
+        beside its restricted fine run and started from the equilibrium of
+        R_0, advance `seg` steps per iteration; the loss is the weighted mean
+        square state error of the conserved densities over those steps, and
+        its gradient comes back through every corrected step (adjoints of the
+        apply, the network and the fused step; truncated at the segment
+        start).  A run restarts on the next training seed after `horizon`
+        steps, or at once if its state stops being finite."""
+        from . import _plbm
+        if self.params is None:
+            self.params = init_params(seed, self.device)
+        p = self.params
+        g = torch.zeros_like(p)
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        B, nc = self.batch, self.nc
+        order = list(seeds)
+        rng = random.Random(seed)
+        rng.shuffle(order)
+        nxt = [0]
+
+        def fresh():
+            s = order[nxt[0] % len(order)]
+            nxt[0] += 1
+            fine = self.fine_lattice(s)
+            return [fine, self.coarse_lattice().init(*self.restricted(fine)), 0]
+
+        runs = [fresh() for _ in range(B)]
+        nbuf = nc * nc * 25
+        lam = [torch.zeros(nbuf, dtype=torch.float64, device=self.device) for _ in range(B)]
+        tmp = [torch.zeros_like(l) for l in lam]
+        scale = 1.0 / (seg * B * nc * nc)
+        hist = []
+        for it in range(1, iters + 1):
+            post = [[r[1].f.clone() for r in runs]]
+            pre, truth = [], []
+            for _ in range(seg):
+                for r in runs:
+                    r[0].step(self.factor)
+                    r[1].step(1)
+                pre.append([r[1].f.clone() for r in runs])
+                self.net.forward(p, [r[1].f for r in runs])
+                self.net.apply([r[1].f for r in runs], bound=float("inf"))
+                post.append([r[1].f.clone() for r in runs])
+                truth.append([self.restricted(r[0]) for r in runs])
+            # backward through the segment
+            for l in lam:
+                l.zero_()
+            loss = 0.0
+            for s in range(seg, 0, -1):
+                try:
+                    loss += self.net.rollout_loss(post[s], truth[s - 1], scale, lam)
+                except _plbm.PlbmError as e:
+                    if e.status != _plbm.PLBM_ENONFINITE:
+                        raise
+                    loss = math.inf          # a run left the finite states: no update
+                    break
+                self.net.forward(p, pre[s - 1])
+                self.net.apply_vjp(pre[s - 1], lam)
+                self.net.backward_vjp(p, g, accumulate=(s != seg), lams=lam, reg=reg)
+                for b in range(B):
+                    _plbm.step_vjp(runs[b][1].desc, post[s - 1][b], lam[b], tmp[b],
+                                   runs[b][1].stream)
+                lam, tmp = tmp, lam
+            if math.isfinite(loss):
+                self.net.adam(p, g, m, v, it, lr=lr * min(1.0, it / 50.0))
+            hist.append((it, loss))
+            if log and (it % 50 == 0 or it == 1):
+                log(f"closure rollout training: iteration {it}, segment loss {loss:.4g}")
+            for b, r in enumerate(runs):
+                r[2] += seg
+                if r[2] >= horizon or not math.isfinite(loss) or \
+                        not bool(torch.isfinite(post[-1][b][:1024]).all()):
+                    runs[b] = fresh()
+        torch.cuda.synchronize(self.device)
+        return hist
+
     # -- judging ---------------------------------------------------------
-    def judge(self, seed, steps, every, bound=None):
+    def net_for(self, storage=None):
+        """The network's workspaces for coarse lattices of `storage` (same
+        parameters and normalisation)."""
+        if storage is None or storage == self.storage:
+            return self.net
+        if not hasattr(self, "_other"):
+            self._other = {}
+        if storage not in self._other:
+            self._other[storage] = Closure(self.nc, self.nc, self.batch, self.device, storage=storage)
+            self._other[storage].set_norm(*self.norm)
+        return self._other[storage]
+
+    def judge(self, seed, steps, every, bound=None, storage=None):
         """Relative L2 errors (rho, |u|, theta) of plain and corrected coarse
         runs against the restricted fine run, averaged over t = every,
-        2 every, ..., steps."""
+        2 every, ..., steps (coarse populations in `storage`, default the
+        experiment's)."""
+        net = self.net_for(storage)
         fine = self.fine_lattice(seed)
         r0 = self.restricted(fine)
-        plain = self.coarse_lattice().init(*r0)
-        corr = self.coarse_lattice().init(*r0)
+        plain = self.coarse_lattice(storage).init(*r0)
+        corr = self.coarse_lattice(storage).init(*r0)
         bound = self.bound if bound is None else bound
         skipped = torch.zeros(1, dtype=torch.int32, device=self.device)
         err = {"plain": [0.0, 0.0, 0.0], "closure": [0.0, 0.0, 0.0]}
@@ -198,8 +343,8 @@ class Experiment:
             fine.step(self.factor)
             plain.step(1)
             corr.step(1)
-            self.net.forward(self.params, [corr.f])
-            self.net.apply([corr.f], bound=bound, skipped=skipped)
+            net.forward(self.params, [corr.f])
+            net.apply([corr.f], bound=bound, skipped=skipped)
             if n % every:
                 continue
             k += 1
@@ -237,58 +382,71 @@ def forward_rate(ex, reps=20):
 
 
 def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 220),
-        per_seed=10, horizon=500, iters=2000, batch=8, lr=1e-3, judge_steps=500,
-        judge_every=50, input_noise=0.5, kmin=3, log=None):
-    """The full learned-closure experiment: generate, train, judge."""
+        iters=600, seg=32, batch=8, lr=2e-4, judge_steps=500, judge_every=50, storage="f32",
+        log=None):
+    """The full learned-closure experiment: normalise, train through
+    coarse steps, judge.
+
+    Normalisation comes from one-step frames of 8 training seeds and the
+    plain run's state errors on 4 of them.  The network starts from a zero
+    output layer (the plain step) and is trained by train_rollout on the
+    training seeds; the fallback bound is calibrated on corrected rollouts of
+    two training seeds.  The judge runs every held-out seed for judge_steps
+    coarse steps from the equilibrium of R_0, plain and corrected, in the
+    coarse storage of the experiment and, with the same network, in the
+    other one (FP32 / FP64)."""
     import time
     say = log or (lambda msg: None)
-    ex = Experiment(n_coarse=n_coarse, factor=factor, batch=batch)
-    t0 = time.perf_counter()
-    ex.generate(held_seeds, 4, horizon, rng_seed=1)
-    held_frames = [f for f in ex.frames if f[2] >= kmin]
-    ex.frames = []
     seeds = list(train_seeds)
-    for i in range(0, len(seeds), 20):
-        ex.generate(seeds[i:i + 20], per_seed, horizon, rng_seed=i)
-        say(f"closure: frames of {min(i + 20, len(seeds))}/{len(seeds)} training seeds")
-    ex.frames = [f for f in ex.frames if f[2] >= kmin]
-    gen_s = time.perf_counter() - t0
-    say(f"closure: {len(ex.frames)} training and {len(held_frames)} held-out frames in {gen_s:.1f} s")
-    ex.fit_norm()
+    ex = Experiment(n_coarse=n_coarse, factor=factor, batch=batch, storage=storage)
     t0 = time.perf_counter()
-    ex.train(iters, lr=lr, input_noise=input_noise)
+    ex.generate(seeds[:8], 4, 100, rng_seed=0)
+    ex.fit_norm()
+    sigma = ex.fit_rollout_scale(seeds[:4], steps=50)
+    setup_s = time.perf_counter() - t0
+    ex.params = init_params(0, ex.device, out_gain=0.0)
+    t0 = time.perf_counter()
+    hist = ex.train_rollout(seeds, iters, seg=seg, lr=lr, log=say)
     train_s = time.perf_counter() - t0
-    # the moment loss on a fixed sample of training frames, without and with
-    # the correction (single mini-batch losses are too noisy to compare)
-    lt_plain, lt_corr, train_explained = ex.explained(ex.frames[:64])
-    say(f"closure: trained {iters} iterations in {train_s:.1f} s; training-sample loss "
-        f"{lt_plain:.4g} (plain step) -> {lt_corr:.4g} (corrected)")
+    say(f"closure: trained {iters} rollout iterations of {seg} steps x {batch} runs in {train_s:.1f} s")
+    # one-step skill on held-out frames (the moment loss of a single step)
+    ex.frames = []
+    ex.generate(held_seeds, 4, judge_steps, rng_seed=1)
+    held_frames = [f for f in ex.frames if f[2] >= 3]
     l_plain, l_corr, explained = ex.explained(held_frames)
-    say(f"closure: held-out one-step error explained {explained:.3f}")
-    bound = ex.calibrate_bound(ex.frames[:64])
-    say(f"closure: fallback bound {bound:.4g}")
+    bound = ex.calibrate_bound_rollout(seeds[:2])
+    say(f"closure: held-out one-step error explained {explained:.3f}; fallback bound {bound:.4g}")
     fwd_ms, fwd_tflops = forward_rate(ex)
-    judged = []
-    for s in held_seeds:
-        judged.append(ex.judge(s, judge_steps, judge_every))
-    plain = [sum(j["plain"][i] for j in judged) / len(judged) for i in range(3)]
-    corr = [sum(j["closure"][i] for j in judged) / len(judged) for i in range(3)]
-    return {"coarse": n_coarse, "fine": n_coarse * factor, "omega_c": ex.omega_c,
-            "train_seeds": len(list(train_seeds)), "held_out_seeds": len(judged),
-            "frames": len(ex.frames), "iters": iters, "batch": batch,
-            "restart": ex.restart, "kmin": kmin, "input_noise": input_noise,
-            "train_loss_plain": lt_plain, "train_loss_closure": lt_corr,
-            "train_explained": train_explained,
-            "reg": ex.reg, "held_out_frames": len(held_frames),
-            "one_step_loss_plain": l_plain, "one_step_loss_closure": l_corr,
-            "held_out_explained": explained, "fallback_bound": bound, "gen_s": gen_s,
-            "train_s": train_s, "ms_per_iter": 1e3 * train_s / iters,
-            "forward_ms_per_batch": fwd_ms, "forward_tflops": fwd_tflops,
-            "judge_steps": judge_steps,
-            "rel_l2_plain": {"rho": plain[0], "u": plain[1], "theta": plain[2]},
-            "rel_l2_closure": {"rho": corr[0], "u": corr[1], "theta": corr[2]},
-            "gain": {"rho": plain[0] / corr[0], "u": plain[1] / corr[1],
-                     "theta": plain[2] / corr[2]},
-            "skipped_nodes": sum(j["skipped_nodes"] for j in judged),
-            "node_steps": len(judged) * judge_steps * n_coarse * n_coarse,
-            "finite": all(j["finite"] for j in judged)}
+    other = "f64" if storage == "f32" else "f32"
+    out = {"coarse": n_coarse, "fine": n_coarse * factor, "omega_c": ex.omega_c,
+           "storage": storage, "train_seeds": len(seeds), "held_out_seeds": len(list(held_seeds)),
+           "training": "through coarse steps (adjoint of the step, apply and network)",
+           "iters": iters, "segment": seg, "batch": batch, "lr": lr,
+           "rollout_sigma": sigma, "setup_s": setup_s, "train_s": train_s,
+           "ms_per_iter": 1e3 * train_s / iters,
+           "loss_first_last": [hist[0][1], hist[-1][1]],
+           "one_step_loss_plain": l_plain, "one_step_loss_closure": l_corr,
+           "held_out_explained": explained, "fallback_bound": bound,
+           "forward_ms_per_batch": fwd_ms, "forward_tflops": fwd_tflops,
+           "judge_steps": judge_steps}
+    for st in (storage, other):
+        judged = [ex.judge(s, judge_steps, judge_every, storage=st) for s in held_seeds]
+        plain = [sum(j["plain"][i] for j in judged) / len(judged) for i in range(3)]
+        corr = [sum(j["closure"][i] for j in judged) / len(judged) for i in range(3)]
+        gains = [[j["plain"][i] / j["closure"][i] for i in range(3)] for j in judged]
+        res = {"rel_l2_plain": {"rho": plain[0], "u": plain[1], "theta": plain[2]},
+               "rel_l2_closure": {"rho": corr[0], "u": corr[1], "theta": corr[2]},
+               "gain": {"rho": plain[0] / corr[0], "u": plain[1] / corr[1],
+                        "theta": plain[2] / corr[2]},
+               "min_seed_gain": {"rho": min(g[0] for g in gains), "u": min(g[1] for g in gains),
+                                 "theta": min(g[2] for g in gains)},
+               "skipped_nodes": sum(j["skipped_nodes"] for j in judged),
+               "node_steps": len(judged) * judge_steps * n_coarse * n_coarse,
+               "finite": all(j["finite"] for j in judged)}
+        say(f"closure: judged in {st}: gain rho {res['gain']['rho']:.3f}, u {res['gain']['u']:.3f}, "
+            f"theta {res['gain']['theta']:.3f}")
+        if st == storage:
+            out.update(res)
+        else:
+            out["judged_in_" + st] = res
+    return out
