@@ -58,15 +58,18 @@ def test_step_f64_matches_oracle(zeta, nx, ny, steps):
     assert rel_err(_pulled(lat), f) < 1e-12
 
 
-@pytest.mark.parametrize("zeta,omega", [(3.0, 1.99880), (4.0, 1.998614)])
-def test_shear_layer_f64_matches_oracle(zeta, omega):
-    """The paper's 128^2 shear layer (Sec. 3.2) for 200 steps."""
-    n, s = 128, np.sqrt(3.0 / zeta)
-    fields = inputs.kelvin_helmholtz(n, n, u0=0.069 * s, delta=n / 80.0, theta=1 / zeta,
-                                     uy_amp=0.05 * 0.069 * s, phase=np.pi / 2)
-    _, got, ref, _ = _run(n, n, zeta, omega, 200, fields)
+@pytest.mark.parametrize("zeta,omega,steps", [(3.0, 1.99880, 500), (4.0, 1.998614, 577)])
+def test_shear_layer_f64_matches_oracle(zeta, omega, steps):
+    """The paper's 128^2 shear layer (Sec. 3.2; u0 = 0.069 in units of
+    sqrt(theta0), i.e. 0.069 / sqrt(zeta) in lattice units) to the first step
+    pair of its figure (LBGK 500, zeta = 4 577)."""
+    n = 128
+    u0 = 0.069 / np.sqrt(zeta)
+    fields = inputs.kelvin_helmholtz(n, n, u0=u0, delta=n / 80.0, theta=1 / zeta,
+                                     uy_amp=0.05 * u0, phase=np.pi / 2)
+    _, got, ref, _ = _run(n, n, zeta, omega, steps, fields)
     assert rel_err(got[0], ref[0]) < 1e-12
-    assert max(rel_err(got[1], ref[1], 0.069), rel_err(got[2], ref[2], 0.069)) < 1e-12
+    assert max(rel_err(got[1], ref[1], u0), rel_err(got[2], ref[2], u0)) < 1e-12
 
 
 def test_step_f32_matches_oracle():
