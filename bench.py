@@ -164,7 +164,7 @@ def summarize(times, nodes, bytes_step):
                            bytes_step / (min(times) * 1e-3) / 1e9 / HBM_PEAK_GBS]}
 
 
-PREWARM_MS = 60.0
+PREWARM_MS = 100.0
 
 
 def device_prewarm(storage, n, fields, theta, ms=PREWARM_MS):
@@ -186,8 +186,9 @@ def device_prewarm(storage, n, fields, theta, ms=PREWARM_MS):
         e1.record(st)
         e1.synchronize()
         done += e0.elapsed_time(e1)
+    # (the scratch buffers go back to torch's cache, not to the driver: no
+    # idle gap before the timed lattice starts)
     del scratch
-    torch.cuda.empty_cache()
 
 
 def time_form(storage, n, fields, steps, warmup, theta):
