@@ -146,3 +146,66 @@ def test_apply_vjp_and_network_backward_match_oracle(net_setup):
         dy = (s["oscale"] * dc) @ Ph
         assert np.abs(dy3[f] - dy).max() <= 2.0 ** -7 * np.abs(dy).max(), f
     assert torch.isfinite(grads).all() and float(grads.abs().max()) > 0
+
+
+def test_rollout_gradient_matches_finite_differences():
+    """The whole chain the closure's training uses (the loss over a segment of
+    corrected steps, back through each apply, the network and the fused
+    step), as a directional derivative along the last layer's weights,
+    against central differences of the segment loss.  The network runs in
+    bf16, so the step is large (5 % of the weights) and the bound 5 %."""
+    from paper_1402_5487_amd import closure_train as ct
+    n, seg, B = 64, 4, 2
+    ex = ct.Experiment(n_coarse=n, factor=4, batch=B)
+    ex.generate(range(2), 4, 40, rng_seed=0)
+    ex.fit_norm()
+    ex.fit_rollout_scale(range(2), steps=20)
+    p = init_params(0, ex.device, out_gain=1.0)
+    fines = [ex.fine_lattice(s) for s in (3, 4)]
+    coarses = [ex.coarse_lattice().init(*ex.restricted(f)) for f in fines]
+    for f, c in zip(fines, coarses):
+        f.step(4 * 5)
+        c.step(5)
+    start = [c.f.clone() for c in coarses]
+    truth = []
+    for _ in range(seg):
+        for f in fines:
+            f.step(4)
+        truth.append([ex.restricted(f) for f in fines])
+    scale = 1.0 / (seg * B * n * n)
+
+    def run(params, grad=None):
+        for c, s0 in zip(coarses, start):
+            c.f.copy_(s0)
+        post, pre = [[c.f.clone() for c in coarses]], []
+        for _ in range(seg):
+            for c in coarses:
+                c.step(1)
+            pre.append([c.f.clone() for c in coarses])
+            ex.net.forward(params, [c.f for c in coarses])
+            ex.net.apply([c.f for c in coarses], bound=float("inf"))
+            post.append([c.f.clone() for c in coarses])
+        loss = sum(ex.net.rollout_loss(post[s], truth[s - 1], scale) for s in range(1, seg + 1))
+        if grad is not None:
+            lam = [torch.zeros(n * n * 25, dtype=torch.float64, device="cuda") for _ in range(B)]
+            tmp = [torch.zeros_like(x) for x in lam]
+            for s in range(seg, 0, -1):
+                ex.net.rollout_loss(post[s], truth[s - 1], scale, lam, want_loss=False)
+                ex.net.forward(params, pre[s - 1])
+                ex.net.apply_vjp(pre[s - 1], lam)
+                ex.net.backward_vjp(params, grad, accumulate=(s != seg), lams=lam)
+                for b in range(B):
+                    _plbm.step_vjp(coarses[b].desc, post[s - 1][b], lam[b], tmp[b], coarses[b].stream)
+                lam, tmp = tmp, lam
+        return loss
+
+    g = torch.zeros_like(p)
+    run(p, g)
+    w3 = slice(2 * 9248, 2 * 9248 + 9216)
+    d = torch.zeros_like(p)
+    d[w3] = torch.randn(9216, generator=torch.Generator(device="cuda").manual_seed(9),
+                        device="cuda") * p[w3].abs().max()
+    h = 0.05
+    fd = (run(p + h * d) - run(p - h * d)) / (2 * h)
+    adj_dir = float((g * d).sum())
+    assert abs(fd / adj_dir - 1) < 0.05, (fd, adj_dir)

@@ -30,8 +30,8 @@ def test_rest_state_stays_at_rest_in_16_bit_storage(storage):
     """At the deviation base the stored deviations start at zero; the FP32
     collision of the rest state reproduces it up to FP32 rounding, so 50
     steps leave rho, u and theta at rest to 1e-6 (the planes' scale is the
-    2^-30 floor of a zero deviation, so the deviations hold FP32 rounding
-    noise, not drift)."""
+    floor 2^-26 rho0 of a zero deviation, so the deviations hold FP32
+    rounding noise, not drift)."""
     th = 0.35
     lat = Lattice(2, 300, 20, omega=1.8, storage=storage, theta0=th).init(*_rest(300, 20, th))
     assert int((lat.f.view(torch.int16) & 0x7fff).count_nonzero()) == 0
