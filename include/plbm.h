@@ -528,6 +528,43 @@ int plbm_closure_apply_vjp(plbm_closure *c, void *const *post, double *const *la
 int plbm_closure_backward_vjp(plbm_closure *c, const float *params, float reg, float *grads,
                               int accumulate, double *const *lam, void *stream);
 
+/*
+ * plbm_closure_rollout_vjp -- one backward step of training through
+ * corrected coarse steps, fused: for step s of a segment, with Q_s the
+ * state after the apply of step s, B_(s-1) the buffer the coarse step read
+ * and A_(s-1) the buffer it wrote (the network's input, as given to the last
+ * plbm_closure_forward), it computes what plbm_closure_rollout_loss (at
+ * Q_s), plbm_closure_apply_vjp, plbm_closure_backward_vjp and plbm_step_vjp
+ * compute in sequence, with the same additions in the same order, in two
+ * node passes instead of six (the three in-place passes over the adjoint
+ * buffers become reads of per-node moment cotangents).
+ *   coarse  : the coarse lattice's descriptor (its omega; shape, storage and
+ *             velocities must be the closure's, else PLBM_EINVAL)
+ *   params, reg, grads : as plbm_closure_backward_vjp; accumulate = 0 on
+ *             the first call of a segment writes the parameter gradient and
+ *             restarts the segment loss, non-zero adds to both
+ *   after   : `frames` device buffers Q_s;  truth : 4 * frames FP64 planes
+ *             as plbm_closure_rollout_loss;  scale > 0 as there
+ *   pre     : the buffers A_(s-1) (must be those of the last forward)
+ *   before  : the buffers B_(s-1) (needed only with lam_out)
+ *   lam_in  : NULL (zero: the segment's last step), or `frames` FP64
+ *             adjoint buffers dL/dQ_s from the later steps (read only)
+ *   lam_out : NULL (the segment's first step: its adjoint is truncated), or
+ *             `frames` FP64 adjoint buffers receiving dL/dQ_(s-1) (written;
+ *             must not alias lam_in)
+ *   loss    : NULL, or a host double receiving the segment loss accumulated
+ *             since the last call with accumulate = 0 (synchronises
+ *             `stream`; PLBM_ENONFINITE if not finite).  The partial sums
+ *             live in the closure and plbm_closure_rollout_loss reuses
+ *             them: do not interleave the two within a segment.
+ * Asynchronous otherwise.
+ */
+int plbm_closure_rollout_vjp(plbm_closure *c, const plbm_desc *coarse, const float *params, float reg,
+                             float *grads, int accumulate, void *const *after,
+                             const double *const *truth, double scale, void *const *pre,
+                             const void *const *before, const double *const *lam_in,
+                             double *const *lam_out, int frames, double *loss, void *stream);
+
 /* Device pointer and size of an internal buffer (for tests):
  * 0 input, 1 layer-1 output, 2 layer-2 output (bf16 NHWC x 32), 3 network
  * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs,

@@ -327,6 +327,10 @@ def _setup_closure(lib):
     lib.plbm_closure_apply_vjp.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp]
     lib.plbm_closure_backward_vjp.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int,
                                               ctypes.POINTER(vp), vp]
+    lib.plbm_closure_rollout_vjp.argtypes = [vp, P, vp, ctypes.c_float, vp, ctypes.c_int,
+                                             ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
+                                             ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), ctypes.c_int, D, vp]
 
 
 _setup_closure(lib)
@@ -334,4 +338,5 @@ EXPORTED = EXPORTED + ("plbm_closure_create", "plbm_closure_destroy", "plbm_clos
                        "plbm_closure_forward", "plbm_closure_backward", "plbm_closure_adam",
                        "plbm_closure_apply", "plbm_closure_activation", "plbm_closure_target",
                        "plbm_restrict", "plbm_step_vjp", "plbm_closure_rollout_loss",
-                       "plbm_closure_apply_vjp", "plbm_closure_backward_vjp")
+                       "plbm_closure_apply_vjp", "plbm_closure_backward_vjp",
+                       "plbm_closure_rollout_vjp")

@@ -139,6 +139,26 @@ class Closure:
             1 if accumulate else 0, None if lams is None else _ptrs(lams), _stream(self.device)),
             "plbm_closure_backward_vjp")
 
+    def rollout_vjp(self, desc, params, grads, accumulate, after, truths, scale, pre,
+                    before=None, lam_in=None, lam_out=None, want_loss=False, reg=0.0):
+        """One fused backward step of rollout training (plbm_closure_rollout_vjp):
+        desc the coarse lattice's descriptor; after the states the loss reads,
+        truths their (rho, ux, uy, theta) tuples; pre the buffers of the last
+        forward; before the buffers the coarse step read; lam_in dL/dafter
+        from later steps (None: zero); lam_out receives dL/dbefore (None:
+        skipped).  Returns the segment loss so far when want_loss."""
+        n = len(after)
+        flat = [t for tr in truths for t in tr]
+        loss = ctypes.c_double() if want_loss else None
+        _plbm.check(_plbm.lib.plbm_closure_rollout_vjp(
+            self.handle, ctypes.byref(desc), ctypes.c_void_p(params.data_ptr()), float(reg),
+            ctypes.c_void_p(grads.data_ptr()), 1 if accumulate else 0, _ptrs(after), _ptrs(flat),
+            float(scale), _ptrs(pre), None if before is None else _ptrs(before),
+            None if lam_in is None else _ptrs(lam_in), None if lam_out is None else _ptrs(lam_out),
+            n, ctypes.byref(loss) if want_loss else None, _stream(self.device)),
+            "plbm_closure_rollout_vjp")
+        return loss.value if want_loss else None
+
     def activation(self, which):
         """Copy of an internal buffer: bf16 NHWC (which 0..2, 4..6) as float32
         (frames, ny, nx, 32), the FP32 output (3), the physical correction

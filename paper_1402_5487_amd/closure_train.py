@@ -154,17 +154,17 @@ class Experiment:
 
     def loss_on(self, frames, params=None):
         """Mean moment loss (without the minimum-norm term) over `frames`
-        (whole batches) with `params` (default: the trained ones; zeros give
+        (batches of up to `batch` frames) with `params` (default: the trained ones; zeros give
         the loss of the plain step)."""
         params = self.params if params is None else params
         g = torch.zeros_like(params)
-        tot, nb = 0.0, 0
-        for i in range(0, len(frames) - self.batch + 1, self.batch):
-            self.net.forward(params, [f[0] for f in frames[i:i + self.batch]])
-            tot += self.net.backward(params, [f[1] for f in frames[i:i + self.batch]], g,
-                                     want_loss=True)
-            nb += 1
-        return tot / max(1, nb)
+        tot = 0.0
+        for i in range(0, len(frames), self.batch):
+            chunk = frames[i:i + self.batch]
+            self.net.forward(params, [f[0] for f in chunk])
+            # the library's loss is the mean over the chunk's frames
+            tot += len(chunk) * self.net.backward(params, [f[1] for f in chunk], g, want_loss=True)
+        return tot / len(frames) if frames else math.nan
 
     def explained(self, frames):
         """(L(no correction), L(trained), 1 - ratio) of the moment loss on
@@ -172,7 +172,7 @@ class Experiment:
         step removes."""
         zero = torch.zeros_like(self.params)
         l0, l1 = self.loss_on(frames, zero), self.loss_on(frames)
-        return l0, l1, 1.0 - l1 / l0
+        return l0, l1, (1.0 - l1 / l0) if l0 > 0 else math.nan
 
     def calibrate_bound_rollout(self, seeds, steps=100, factor=4.0):
         """Fallback bound from corrected rollouts of training seeds: `factor`
@@ -264,8 +264,8 @@ class Experiment:
 
         runs = [fresh() for _ in range(B)]
         nbuf = nc * nc * 25
-        lam = [torch.zeros(nbuf, dtype=torch.float64, device=self.device) for _ in range(B)]
-        tmp = [torch.zeros_like(l) for l in lam]
+        lam = [torch.empty(nbuf, dtype=torch.float64, device=self.device) for _ in range(B)]
+        tmp = [torch.empty_like(l) for l in lam]
         scale = 1.0 / (seg * B * nc * nc)
         hist = []
         for it in range(1, iters + 1):
@@ -280,24 +280,24 @@ class Experiment:
                 self.net.apply([r[1].f for r in runs], bound=float("inf"))
                 post.append([r[1].f.clone() for r in runs])
                 truth.append([self.restricted(r[0]) for r in runs])
-            # backward through the segment
-            for l in lam:
-                l.zero_()
+            # backward through the segment (one fused call per step; the
+            # segment loss stays on the device until the last)
+            desc = runs[0][1].desc
             loss = 0.0
             for s in range(seg, 0, -1):
+                self.net.forward(p, pre[s - 1])
                 try:
-                    loss += self.net.rollout_loss(post[s], truth[s - 1], scale, lam)
+                    got = self.net.rollout_vjp(
+                        desc, p, g, s != seg, post[s], truth[s - 1], scale, pre[s - 1],
+                        before=post[s - 1] if s > 1 else None,
+                        lam_in=lam if s != seg else None, lam_out=tmp if s > 1 else None,
+                        want_loss=(s == 1), reg=reg)
                 except _plbm.PlbmError as e:
                     if e.status != _plbm.PLBM_ENONFINITE:
                         raise
-                    loss = math.inf          # a run left the finite states: no update
-                    break
-                self.net.forward(p, pre[s - 1])
-                self.net.apply_vjp(pre[s - 1], lam)
-                self.net.backward_vjp(p, g, accumulate=(s != seg), lams=lam, reg=reg)
-                for b in range(B):
-                    _plbm.step_vjp(runs[b][1].desc, post[s - 1][b], lam[b], tmp[b],
-                                   runs[b][1].stream)
+                    got = math.inf           # a run left the finite states: no update
+                if s == 1:
+                    loss = got
                 lam, tmp = tmp, lam
             if math.isfinite(loss):
                 self.net.adam(p, g, m, v, it, lr=lr * min(1.0, it / 50.0))

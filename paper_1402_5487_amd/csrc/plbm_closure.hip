@@ -808,16 +808,15 @@ __device__ __forceinline__ int wrap(int i, int n)
     return i - (i >= n ? n : 0);
 }
 
-// Step adjoint, one node per thread: from lam = dL/dP' at node x and the
-// conserved densities of S(x) = pull(P)(x), mu = (1 - w) lam + w Phi J^T lam,
-// scattered to dL/dP(x - v_k)_k = mu_k (each target written exactly once).
+// Step adjoint at node x: from l = dL/dP'(x) and the conserved densities of
+// S(x) = pull(P)(x), mu = (1 - w) l + w Phi J^T l, scattered to
+// dL/dP(x - v_k)_k = mu_k (each target written exactly once).
+// Conserved densities of S(x) = pull(P)(x)
 template <typename T>
-__global__ __launch_bounds__(256) void k_step_vjp(const T *__restrict__ P, const double *__restrict__ lam,
-                                                  double *__restrict__ out, int nx, int ny, KParams kp)
+__device__ __forceinline__ void step_moments(const T *__restrict__ P, int x, int y, int nx, int ny,
+                                             const KParams &kp, double (&m)[4])
 {
-    const int y = blockIdx.y, x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= nx) return;
-    double m[4] = {0.0, 0.0, 0.0, 0.0}, l[NQ];
+    m[0] = m[1] = m[2] = m[3] = 0.0;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
         const int vx = kp.sx[k % Q], vy = kp.sx[k / Q];
@@ -826,8 +825,16 @@ __global__ __launch_bounds__(256) void k_step_vjp(const T *__restrict__ P, const
         m[1] += vx * f;
         m[2] += vy * f;
         m[3] += (vx * vx + vy * vy) * f;
-        l[k] = lam[((size_t)y * NQ + k) * nx + x];
     }
+}
+
+// Step adjoint at node x: from l = dL/dP'(x) and the conserved densities m
+// of S(x), mu = (1 - w) l + w Phi J^T l, scattered to dL/dP(x - v_k)_k =
+// mu_k (each target written exactly once).
+__device__ __forceinline__ void step_vjp_scatter(const double (&m)[4], const double (&l)[NQ],
+                                                 double *__restrict__ out, int x, int y, int nx, int ny,
+                                                 const KParams &kp)
+{
     double a[4];
     feq_vjp(kp.r64, m, l, a);
     const double w = kp.r64.omega;
@@ -839,13 +846,73 @@ __global__ __launch_bounds__(256) void k_step_vjp(const T *__restrict__ P, const
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_step_vjp(const T *__restrict__ P, const double *__restrict__ lam,
+                                                  double *__restrict__ out, int nx, int ny, KParams kp)
+{
+    const int y = blockIdx.y, x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    double m[4], l[NQ];
+    step_moments(P, x, y, nx, ny, kp, m);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) l[k] = lam[((size_t)y * NQ + k) * nx + x];
+    step_vjp_scatter(m, l, out, x, y, nx, ny, kp);
+}
+
+// Phi_k . a for a per-node moment cotangent a = (a_rho, a_jx, a_jy, a_E)
+__device__ __forceinline__ double phi_dot(double vx, double vy, const double *__restrict__ a)
+{
+    return a[0] + vx * a[1] + vy * a[2] + (vx * vx + vy * vy) * a[3];
+}
+
 // Up to MAX_FRAMES sets of (rho, u_x, u_y, theta) planes.
 struct TruthList {
     const double *p[4 * MAX_FRAMES];
 };
 
-// Rollout loss at one step: residual r = m(pull(P)) - cons(R) per node and
-// moment, a = 2 scale w r (double4 per node), loss partials scale w r^2.
+// Rollout loss at node x: residual r = m(pull(P))(x) - cons(R)(x) per
+// moment; a = 2 scale w r, returns scale sum_j w_j r_j^2.
+template <typename T>
+__device__ __forceinline__ double rloss_node(const T *__restrict__ P, const TruthList &truth, int f, int x, int y,
+                                             int nx, int ny, const ClNorm &nm, double scale, double (&a)[4])
+{
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k) {
+        const double v = (double)P[((size_t)wrap(y - nm.ivy[k], ny) * CREAL + k) * nx + wrap(x - nm.ivx[k], nx)];
+        const double vx = nm.ivx[k], vy = nm.ivy[k];
+        m[0] += v;
+        m[1] += vx * v;
+        m[2] += vy * v;
+        m[3] += (vx * vx + vy * vy) * v;
+    }
+    const size_t at = (size_t)y * nx + x;
+    const double r0 = truth.p[4 * f][at], u = truth.p[4 * f + 1][at], w = truth.p[4 * f + 2][at],
+                 t = truth.p[4 * f + 3][at];
+    const double c[4] = {r0, r0 * u, r0 * w, r0 * (2.0 * t + u * u + w * w)};
+    double lsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double r = m[j] - c[j];
+        lsum += scale * (double)nm.mw2[j] * r * r;
+        a[j] = 2.0 * scale * (double)nm.mw2[j] * r;
+    }
+    return lsum;
+}
+
+// Sum of one value per thread over a 256-thread block, in a fixed order;
+// the result is valid in thread 0.
+__device__ __forceinline__ double block_sum256(double v, double (&red)[4])
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Rollout loss at one step: a = 2 scale w r (double4 per node) and the
+// loss partials scale w r^2 per block.
 template <typename T>
 __global__ __launch_bounds__(256) void k_cl_rloss(PtrList post, TruthList truth, int nx, int ny, ClNorm nm,
                                                   double scale, double *__restrict__ A,
@@ -856,40 +923,15 @@ __global__ __launch_bounds__(256) void k_cl_rloss(PtrList post, TruthList truth,
     const int x = blockIdx.x * 256 + threadIdx.x;
     double lsum = 0.0;
     if (x < nx) {
-        const T *P = static_cast<const T *>(post.p[f]);
-        double m[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < CREAL; ++k) {
-            const double v = (double)P[((size_t)wrap(y - nm.ivy[k], ny) * CREAL + k) * nx +
-                                       wrap(x - nm.ivx[k], nx)];
-            const double vx = nm.ivx[k], vy = nm.ivy[k];
-            m[0] += v;
-            m[1] += vx * v;
-            m[2] += vy * v;
-            m[3] += (vx * vx + vy * vy) * v;
-        }
-        const size_t at = (size_t)y * nx + x;
-        const double r0 = truth.p[4 * f][at], u = truth.p[4 * f + 1][at], w = truth.p[4 * f + 2][at],
-                     t = truth.p[4 * f + 3][at];
-        const double c[4] = {r0, r0 * u, r0 * w, r0 * (2.0 * t + u * u + w * w)};
         double a[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double r = m[j] - c[j];
-            lsum += scale * (double)nm.mw2[j] * r * r;
-            a[j] = 2.0 * scale * (double)nm.mw2[j] * r;
-        }
-        double *dst = A + ((size_t)f * ny * nx + at) * 4;
+        lsum = rloss_node(static_cast<const T *>(post.p[f]), truth, f, x, y, nx, ny, nm, scale, a);
+        double *dst = A + ((size_t)f * ny * nx + (size_t)y * nx + x) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) dst[j] = a[j];
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
-    __syncthreads();
+    const double tot = block_sum256(lsum, red);
     if (threadIdx.x == 0)
-        lpart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] =
-            (red[0] + red[1]) + (red[2] + red[3]);
+        lpart[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
 // lam(y)_k += Phi_k . a(y + v_k): the push of per-node moment cotangents
@@ -904,33 +946,28 @@ __global__ __launch_bounds__(256) void k_cl_push4(const double *__restrict__ A, 
 #pragma unroll
     for (int k = 0; k < CREAL; ++k) {
         const double *a = Af + ((size_t)wrap(y + nm.ivy[k], ny) * nx + wrap(x + nm.ivx[k], nx)) * 4;
-        const double vx = nm.ivx[k], vy = nm.ivy[k];
-        L[((size_t)y * CREAL + k) * nx + x] += a[0] + vx * a[1] + vy * a[2] + (vx * vx + vy * vy) * a[3];
+        L[((size_t)y * CREAL + k) * nx + x] += phi_dot(nm.ivx[k], nm.ivy[k], a);
     }
 }
 
-// Shift adjoint, per node: Lam = pull(lam)(x), m from pull(P), g from c (as
-// k_cl_shift); writes a_g = J_F(m + g)^T Lam as the moment cotangent of the
-// correction (float4, read by k_cl_mgrad) and a_m = a_g - J_F(m)^T Lam
-// (double4, pushed into lam by k_cl_push4).  Nodes the forward left
-// unshifted (density or temperature not positive) pass nothing.
+// Shift adjoint at node x from Lam = l (the adjoint of the shifted state,
+// already pulled): m from pull(P), g from c (as k_cl_shift); writes
+// a_g = J_F(m + g)^T Lam as the moment cotangent of the correction (float4,
+// read by k_cl_mgrad) and a_m = a_g - J_F(m)^T Lam (double4, the state
+// path).  Nodes the forward left unshifted (density or temperature not
+// positive) pass nothing.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cl_shift_vjp(PtrList post, PtrList lam, const float *__restrict__ C,
-                                                      int nx, int ny, ClNorm nm, KParams kp,
-                                                      float *__restrict__ Ag, double *__restrict__ Am)
+__device__ __forceinline__ void shift_vjp_node(const T *__restrict__ P, const double (&l)[NQ],
+                                               const float *__restrict__ C, int f, int x, int y, int nx, int ny,
+                                               const ClNorm &nm, const KParams &kp, float *__restrict__ Ag,
+                                               double (&am)[4], size_t node)
 {
-    const int f = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= nx) return;
     const size_t plane = (size_t)nx * ny;
-    const T *P = static_cast<const T *>(post.p[f]);
-    const double *L = static_cast<const double *>(lam.p[f]);
-    double m[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0}, l[NQ];
+    double m[4] = {0.0, 0.0, 0.0, 0.0}, g[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < CREAL; ++k) {
         const int xs = wrap(x - nm.ivx[k], nx), ys = wrap(y - nm.ivy[k], ny);
         const double v = (double)P[((size_t)ys * CREAL + k) * nx + xs];
-        l[k] = L[((size_t)ys * CREAL + k) * nx + xs];
         const float *ck = C + ((size_t)f * CREAL + k) * plane;
         const double c = (double)ck[(size_t)ys * nx + xs] - (double)ck[(size_t)y * nx + x];
         const double vx = nm.ivx[k], vy = nm.ivy[k], v2 = vx * vx + vy * vy;
@@ -954,10 +991,29 @@ __global__ __launch_bounds__(256) void k_cl_shift_vjp(PtrList post, PtrList lam,
         feq_vjp(kp.r64, m1, l, ag);
         feq_vjp(kp.r64, m, l, a0);
     }
-    const size_t node = (size_t)f * plane + (size_t)y * nx + x;
     reinterpret_cast<float4 *>(Ag)[node] = make_float4((float)ag[0], (float)ag[1], (float)ag[2], (float)ag[3]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Am[node * 4 + j] = ag[j] - a0[j];
+    for (int j = 0; j < 4; ++j) am[j] = ag[j] - a0[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_shift_vjp(PtrList post, PtrList lam, const float *__restrict__ C,
+                                                      int nx, int ny, ClNorm nm, KParams kp,
+                                                      float *__restrict__ Ag, double *__restrict__ Am)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const double *L = static_cast<const double *>(lam.p[f]);
+    double l[NQ];
+#pragma unroll
+    for (int k = 0; k < CREAL; ++k)
+        l[k] = L[((size_t)wrap(y - nm.ivy[k], ny) * CREAL + k) * nx + wrap(x - nm.ivx[k], nx)];
+    const size_t node = (size_t)f * ny * nx + (size_t)y * nx + x;
+    double am[4];
+    shift_vjp_node(static_cast<const T *>(post.p[f]), l, C, f, x, y, nx, ny, nm, kp, Ag, am, node);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Am[node * 4 + j] = am[j];
 }
 
 // The network input is the normalised post-collision buffer at the node
@@ -973,6 +1029,99 @@ __global__ __launch_bounds__(256) void k_cl_input_vjp(const float *__restrict__ 
 #pragma unroll
     for (int k = 0; k < CREAL; ++k)
         L[((size_t)y * CREAL + k) * nx + x] += (double)nm.in_inv[k] * (double)dx[node * CH + k];
+}
+
+// ---------------------------------------------------------------------------
+// One backward step of rollout training in two passes (plbm_closure_rollout_vjp).
+// With lam_in = dL/dQ_s from the later steps (Q_s the state after the apply
+// of step s), the loss at Q_s adds push(Phi A_L) and the apply's state path
+// push(Phi a_m); the network input adds inv * dx.  Seen through the pull at
+// node x, a pushed moment cotangent is the node's own: pull(push(Phi A))(x)_k
+// = Phi_k . A(x).  So
+//   k_cl_rstep_shift: A_L(x) from Q_s, Lam_k = lam_in(x - v_k)_k + Phi_k . A_L(x)
+//     (as k_cl_rloss + k_cl_push4 compute it), then the shift adjoint
+//     (a_g, a_m) from Lam; stores A = A_L + a_m per node;
+//   k_cl_rstep_step:  l_k(x) = (lam_in(x)_k + Phi_k . A(x + v_k)) + inv_k dx_k(x),
+//     then the step adjoint to lam_out = dL/dQ_(s-1),
+// without the three read-modify-write passes over lam that the separate
+// calls make (the two pushes are summed per node before they are pushed,
+// a different rounding of the same terms).  Loss partials are added to the
+// block's slot when acc_loss (the segment's loss stays on the device).
+// Scheduling barriers between the phases keep the compiler from hoisting
+// every load of the kernel at once (that took 256 VGPRs and one wave per
+// SIMD).
+// ---------------------------------------------------------------------------
+template <typename T, bool LIN>
+__global__ __launch_bounds__(256) void k_cl_rstep_shift(PtrList after, TruthList truth, PtrList pre, PtrList lam_in,
+                                                        const float *__restrict__ C, int nx, int ny, ClNorm nm,
+                                                        KParams kp, double scale, int acc_loss,
+                                                        float *__restrict__ Ag, double *__restrict__ A,
+                                                        double *__restrict__ lpart)
+{
+    __shared__ double red[4];
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    double lsum = 0.0;
+    if (x < nx) {
+        double a[4];
+        lsum = rloss_node(static_cast<const T *>(after.p[f]), truth, f, x, y, nx, ny, nm, scale, a);
+        __builtin_amdgcn_sched_barrier(0);
+        const double *L = static_cast<const double *>(lam_in.p[f]);
+        double l[NQ];
+#pragma unroll
+        for (int k = 0; k < CREAL; ++k) {
+            const double in = LIN ? L[((size_t)wrap(y - nm.ivy[k], ny) * CREAL + k) * nx + wrap(x - nm.ivx[k], nx)]
+                                  : 0.0;
+            l[k] = in + phi_dot(nm.ivx[k], nm.ivy[k], a);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const size_t node = (size_t)f * ny * nx + (size_t)y * nx + x;
+        double am[4];
+        shift_vjp_node(static_cast<const T *>(pre.p[f]), l, C, f, x, y, nx, ny, nm, kp, Ag, am, node);
+        reinterpret_cast<double4 *>(A)[node] = make_double4(a[0] + am[0], a[1] + am[1], a[2] + am[2], a[3] + am[3]);
+    }
+    const double tot = block_sum256(lsum, red);
+    if (threadIdx.x == 0) {
+        const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        lpart[b] = acc_loss ? lpart[b] + tot : tot;
+    }
+}
+
+template <typename T, bool LIN>
+__global__ __launch_bounds__(256) void k_cl_rstep_step(PtrList before, PtrList lam_in, const double *__restrict__ A,
+                                                       const float *__restrict__ dx, PtrList lam_out, int nx,
+                                                       int ny, ClNorm nm, KParams kp)
+{
+    const int f = blockIdx.z, y = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const size_t fbase = (size_t)f * ny * nx;
+    const double *L = static_cast<const double *>(lam_in.p[f]);
+    double m[4];
+    step_moments(static_cast<const T *>(before.p[f]), x, y, nx, ny, kp, m);
+    __builtin_amdgcn_sched_barrier(0);
+    // the node's 25 input-gradient channels: seven 16-byte loads of its 128-byte row
+    const float4 *d4 = reinterpret_cast<const float4 *>(dx + (fbase + (size_t)y * nx + x) * CH);
+    double l[NQ];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const float4 t = d4[q];
+        const float d[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * q + e;
+            if (k >= CREAL) break;
+            const size_t nb = fbase + (size_t)wrap(y + nm.ivy[k], ny) * nx + wrap(x + nm.ivx[k], nx);
+            const double4 av = reinterpret_cast<const double4 *>(A)[nb];
+            const double a[4] = {av.x, av.y, av.z, av.w};
+            double v = LIN ? L[((size_t)y * CREAL + k) * nx + x] : 0.0;
+            v += phi_dot(nm.ivx[k], nm.ivy[k], a);
+            l[k] = v + (double)nm.in_inv[k] * (double)d[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);     // four neighbours' loads in flight at a time
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    step_vjp_scatter(m, l, static_cast<double *>(lam_out.p[f]), x, y, nx, ny, kp);
 }
 
 // FP32 parameters -> bf16 [t][o][i] (forward) and [t][i][o] (input gradient)
@@ -1467,6 +1616,81 @@ extern "C" int plbm_closure_backward_vjp(plbm_closure *c, const float *params, f
     layers_backward(c, frames, grads, accumulate ? 1 : 0, st, lam != nullptr);
     if (lam) hipLaunchKernelGGL(k_cl_input_vjp, gn, dim3(256), 0, st, c->dx, ll, c->nx, c->ny, c->nm);
     return ck(hipGetLastError());
+}
+
+extern "C" int plbm_closure_rollout_vjp(plbm_closure *c, const plbm_desc *coarse, const float *params, float reg,
+                                        float *grads, int accumulate, void *const *after,
+                                        const double *const *truth, double scale, void *const *pre,
+                                        const void *const *before, const double *const *lam_in,
+                                        double *const *lam_out, int frames, double *loss, void *stream)
+{
+    if (!c || !coarse || !params || !grads || !after || !truth || !pre || frames < 1 ||
+        frames != c->frames_in_fwd || !(scale > 0.0) || !std::isfinite(scale) || !(reg >= 0.f) ||
+        !std::isfinite(reg))
+        return PLBM_EINVAL;
+    // the coarse lattice the step adjoint runs on: the closure's shape, storage and velocities
+    if (coarse->dim != 2 || coarse->nx != c->nx || coarse->ny != c->ny ||
+        (coarse->storage == PLBM_F64) != c->f64 || (coarse->storage != PLBM_F64 && coarse->storage != PLBM_F32) ||
+        plbm::gen_handles(coarse) || coarse->q1d != Q)
+        return PLBM_EINVAL;
+    KParams kp;
+    int rc = make_params(coarse, kp);
+    if (rc != PLBM_OK) return rc;
+    for (int k = 0; k < CREAL; ++k)
+        if (kp.sx[k % Q] != c->nm.ivx[k] || kp.sx[k / Q] != c->nm.ivy[k]) return PLBM_EINVAL;
+    PtrList al, pl, bl, li, lo;
+    rc = make_list(al, after, frames);
+    if (rc == PLBM_OK) rc = make_list(pl, pre, frames);
+    if (rc != PLBM_OK) return rc;
+    std::memset(&li, 0, sizeof(li));
+    if (lam_in) {
+        rc = make_list(li, lam_in, frames);
+        if (rc != PLBM_OK) return rc;
+    }
+    if (lam_out) {
+        if (!before) return PLBM_EINVAL;
+        rc = make_list(bl, before, frames);
+        if (rc == PLBM_OK) rc = make_list(lo, lam_out, frames);
+        if (rc != PLBM_OK) return rc;
+        for (int i = 0; i < frames; ++i)
+            if (lam_in && lam_in[i] == lam_out[i]) return PLBM_EINVAL;
+    }
+    TruthList tl;
+    for (int i = 0; i < 4 * frames; ++i) {
+        if (!truth[i]) return PLBM_EINVAL;
+        tl.p[i] = truth[i];
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const dim3 gn((c->nx + 255) / 256, c->ny, frames);
+    const float inv_n = 1.0f / ((float)frames * c->nx * c->ny);
+    // the correction of the last forward pass, without the fallback bound
+    hipLaunchKernelGGL(k_cl_corr_apply, gn, dim3(256), 0, st, c->y3, c->nx, c->ny, c->nm, INFINITY, c->corr,
+                       nullptr);
+    // lam_in == NULL (zero) and FP32 / FP64 storage are template cases
+    auto shift_kernel = c->f64 ? (lam_in ? k_cl_rstep_shift<double, true> : k_cl_rstep_shift<double, false>)
+                               : (lam_in ? k_cl_rstep_shift<float, true> : k_cl_rstep_shift<float, false>);
+    hipLaunchKernelGGL(shift_kernel, gn, dim3(256), 0, st, al, tl, pl, li, c->corr, c->nx, c->ny, c->nm, c->kp,
+                       scale, accumulate ? 1 : 0, c->mres, c->adj4, c->lpart64);
+    hipLaunchKernelGGL(k_cl_mgrad, gn, dim3(256), 0, st, c->mres, c->y3, c->nx, c->ny, c->nm, 2.f * reg * inv_n,
+                       c->dy3);
+    layers_backward(c, frames, grads, accumulate ? 1 : 0, st, lam_out != nullptr);
+    if (lam_out) {
+        auto step_kernel = c->f64 ? (lam_in ? k_cl_rstep_step<double, true> : k_cl_rstep_step<double, false>)
+                                  : (lam_in ? k_cl_rstep_step<float, true> : k_cl_rstep_step<float, false>);
+        hipLaunchKernelGGL(step_kernel, gn, dim3(256), 0, st, bl, li, c->adj4, c->dx, lo, c->nx, c->ny, c->nm, kp);
+    }
+    rc = ck(hipGetLastError());
+    if (rc != PLBM_OK || !loss) return rc;
+    const int nl = (int)(gn.x * gn.y * gn.z);
+    std::vector<double> h(nl);
+    rc = ck(hipMemcpyAsync(h.data(), c->lpart64, nl * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (rc == PLBM_OK) rc = ck(hipStreamSynchronize(st));
+    if (rc != PLBM_OK) return rc;
+    double sum = 0.0;
+    for (double v : h) sum += v;
+    *loss = sum;
+    return std::isfinite(sum) ? PLBM_OK : PLBM_ENONFINITE;
 }
 
 extern "C" int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes)

@@ -148,64 +148,138 @@ def test_apply_vjp_and_network_backward_match_oracle(net_setup):
     assert torch.isfinite(grads).all() and float(grads.abs().max()) > 0
 
 
-def test_rollout_gradient_matches_finite_differences():
+class _Segment:
+    """A segment of corrected coarse steps beside restricted fine runs (64^2
+    coarse, B runs), its loss and its gradient through every step, by the
+    building-block calls or by the fused plbm_closure_rollout_vjp."""
+
+    def __init__(self, n=64, seg=4, B=2, storage="f64"):
+        from paper_1402_5487_amd import closure_train as ct
+        self.n, self.seg, self.B = n, seg, B
+        ex = ct.Experiment(n_coarse=n, factor=4, batch=B, storage=storage)
+        ex.generate(range(2), 4, 40, rng_seed=0)
+        ex.fit_norm()
+        ex.fit_rollout_scale(range(2), steps=20)
+        self.ex = ex
+        fines = [ex.fine_lattice(s) for s in (3, 4)[:B]]
+        self.coarses = [ex.coarse_lattice().init(*ex.restricted(f)) for f in fines]
+        for f, c in zip(fines, self.coarses):
+            f.step(4 * 5)
+            c.step(5)
+        self.start = [c.f.clone() for c in self.coarses]
+        self.truth = []
+        for _ in range(seg):
+            for f in fines:
+                f.step(4)
+            self.truth.append([ex.restricted(f) for f in fines])
+        self.scale = 1.0 / (seg * B * n * n)
+
+    def forward(self, params):
+        ex, cs = self.ex, self.coarses
+        for c, s0 in zip(cs, self.start):
+            c.f.copy_(s0)
+        self.post, self.pre = [[c.f.clone() for c in cs]], []
+        for _ in range(self.seg):
+            for c in cs:
+                c.step(1)
+            self.pre.append([c.f.clone() for c in cs])
+            ex.net.forward(params, [c.f for c in cs])
+            ex.net.apply([c.f for c in cs], bound=float("inf"))
+            self.post.append([c.f.clone() for c in cs])
+
+    def loss(self, params):
+        self.forward(params)
+        return sum(self.ex.net.rollout_loss(self.post[s], self.truth[s - 1], self.scale)
+                   for s in range(1, self.seg + 1))
+
+    def grad(self, params, fused, keep=None):
+        """Gradient into a new tensor (after forward(params)); keep, if a
+        list, receives dL/dQ_(s-1) for s = seg .. 2.  Returns (grad, loss)."""
+        ex, cs, B, n = self.ex, self.coarses, self.B, self.n
+        g = torch.zeros(3 * 9248, dtype=torch.float32, device="cuda")
+        lam = [torch.zeros(n * n * 25, dtype=torch.float64, device="cuda") for _ in range(B)]
+        tmp = [torch.zeros_like(x) for x in lam]
+        loss = 0.0
+        for s in range(self.seg, 0, -1):
+            if fused:
+                ex.net.forward(params, self.pre[s - 1])
+                got = ex.net.rollout_vjp(
+                    cs[0].desc, params, g, s != self.seg, self.post[s], self.truth[s - 1], self.scale,
+                    self.pre[s - 1], before=self.post[s - 1] if s > 1 else None,
+                    lam_in=lam if s != self.seg else None, lam_out=tmp if s > 1 else None,
+                    want_loss=(s == 1))
+                if s == 1:
+                    loss = got
+            else:
+                loss += ex.net.rollout_loss(self.post[s], self.truth[s - 1], self.scale, lam)
+                ex.net.forward(params, self.pre[s - 1])
+                ex.net.apply_vjp(self.pre[s - 1], lam)
+                ex.net.backward_vjp(params, g, accumulate=(s != self.seg), lams=lam)
+                if s > 1:
+                    for b in range(B):
+                        _plbm.step_vjp(cs[b].desc, self.post[s - 1][b], lam[b], tmp[b], cs[b].stream)
+            if s > 1:
+                if keep is not None:
+                    keep.append([t.clone() for t in tmp])
+                lam, tmp = tmp, lam
+        return g, loss
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fused_rollout_step_matches_the_building_blocks(storage):
+    """plbm_closure_rollout_vjp against the sequence rollout_loss, apply_vjp,
+    backward_vjp, step_vjp it fuses: the same additions in the same order,
+    so the FP64 adjoints of every step agree to the last bit (1e-15 of the
+    largest value allowed for a contraction the compiler may choose
+    differently), the FP32 parameter gradient to 1e-6 (a last-bit change of
+    an FP64 cotangent can move an FP32 rounding), and the segment loss,
+    summed block by block over the steps rather than step by step, to
+    1e-13."""
+    sg = _Segment(seg=3, storage=storage)
+    p = init_params(0, "cuda", out_gain=1.0)
+    sg.forward(p)
+    keep_a, keep_b = [], []
+    ga, la = sg.grad(p, fused=False, keep=keep_a)
+    gb, lb = sg.grad(p, fused=True, keep=keep_b)
+    assert len(keep_a) == len(keep_b) == 2
+    for ka, kb in zip(keep_a, keep_b):
+        for a, b in zip(ka, kb):
+            assert float((a - b).abs().max()) <= 1e-15 * float(a.abs().max()), storage
+    assert float((ga - gb).abs().max()) <= 1e-6 * float(ga.abs().max()), storage
+    assert abs(lb / la - 1) < 1e-13, (la, lb)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_rollout_gradient_matches_finite_differences(fused):
     """The whole chain the closure's training uses (the loss over a segment of
     corrected steps, back through each apply, the network and the fused
     step), as a directional derivative along the last layer's weights,
-    against central differences of the segment loss.  The network runs in
-    bf16, so the step is large (5 % of the weights) and the bound 5 %."""
-    from paper_1402_5487_amd import closure_train as ct
-    n, seg, B = 64, 4, 2
-    ex = ct.Experiment(n_coarse=n, factor=4, batch=B)
-    ex.generate(range(2), 4, 40, rng_seed=0)
-    ex.fit_norm()
-    ex.fit_rollout_scale(range(2), steps=20)
-    p = init_params(0, ex.device, out_gain=1.0)
-    fines = [ex.fine_lattice(s) for s in (3, 4)]
-    coarses = [ex.coarse_lattice().init(*ex.restricted(f)) for f in fines]
-    for f, c in zip(fines, coarses):
-        f.step(4 * 5)
-        c.step(5)
-    start = [c.f.clone() for c in coarses]
-    truth = []
-    for _ in range(seg):
-        for f in fines:
-            f.step(4)
-        truth.append([ex.restricted(f) for f in fines])
-    scale = 1.0 / (seg * B * n * n)
-
-    def run(params, grad=None):
-        for c, s0 in zip(coarses, start):
-            c.f.copy_(s0)
-        post, pre = [[c.f.clone() for c in coarses]], []
-        for _ in range(seg):
-            for c in coarses:
-                c.step(1)
-            pre.append([c.f.clone() for c in coarses])
-            ex.net.forward(params, [c.f for c in coarses])
-            ex.net.apply([c.f for c in coarses], bound=float("inf"))
-            post.append([c.f.clone() for c in coarses])
-        loss = sum(ex.net.rollout_loss(post[s], truth[s - 1], scale) for s in range(1, seg + 1))
-        if grad is not None:
-            lam = [torch.zeros(n * n * 25, dtype=torch.float64, device="cuda") for _ in range(B)]
-            tmp = [torch.zeros_like(x) for x in lam]
-            for s in range(seg, 0, -1):
-                ex.net.rollout_loss(post[s], truth[s - 1], scale, lam, want_loss=False)
-                ex.net.forward(params, pre[s - 1])
-                ex.net.apply_vjp(pre[s - 1], lam)
-                ex.net.backward_vjp(params, grad, accumulate=(s != seg), lams=lam)
-                for b in range(B):
-                    _plbm.step_vjp(coarses[b].desc, post[s - 1][b], lam[b], tmp[b], coarses[b].stream)
-                lam, tmp = tmp, lam
-        return loss
-
-    g = torch.zeros_like(p)
-    run(p, g)
+    against central differences of the segment loss; by the building-block
+    calls and by the fused backward step.  The network runs in bf16, so the
+    step is large (5 % of the weights) and the bound 5 %."""
+    sg = _Segment()
+    p = init_params(0, "cuda", out_gain=1.0)
+    sg.forward(p)
+    g, _ = sg.grad(p, fused)
     w3 = slice(2 * 9248, 2 * 9248 + 9216)
     d = torch.zeros_like(p)
     d[w3] = torch.randn(9216, generator=torch.Generator(device="cuda").manual_seed(9),
                         device="cuda") * p[w3].abs().max()
     h = 0.05
-    fd = (run(p + h * d) - run(p - h * d)) / (2 * h)
+    fd = (sg.loss(p + h * d) - sg.loss(p - h * d)) / (2 * h)
     adj_dir = float((g * d).sum())
     assert abs(fd / adj_dir - 1) < 0.05, (fd, adj_dir)
+
+
+def test_fused_rollout_step_rejects_a_mismatched_lattice():
+    """The descriptor must be the closure's coarse lattice (shape, storage)."""
+    sg = _Segment(seg=1)
+    p = init_params(0, "cuda", out_gain=1.0)
+    sg.forward(p)
+    g = torch.zeros(3 * 9248, dtype=torch.float32, device="cuda")
+    other = _plbm.desc_default(2, 32, 64, 1.9, "f64")
+    with pytest.raises(_plbm.PlbmError):
+        sg.ex.net.rollout_vjp(other, p, g, False, sg.post[1], sg.truth[0], sg.scale, sg.pre[0])
+    wrong_storage = _plbm.desc_default(2, 64, 64, 1.9, "f32")
+    with pytest.raises(_plbm.PlbmError):
+        sg.ex.net.rollout_vjp(wrong_storage, p, g, False, sg.post[1], sg.truth[0], sg.scale, sg.pre[0])

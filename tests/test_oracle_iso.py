@@ -125,8 +125,8 @@ def test_shear_layer_lbgk_and_zeta4_agree_and_zeta4_is_more_stable():
     """Sec. 3.2, Fig. LPViscosityMatch2d at all its step pairs (LBGK step n =
     zeta-4 step n sqrt(4/3)): at 500 / 577 the two models' velocity
     amplitudes agree; at 1500 / 1732 the LBGK run carries several times the
-    zeta-4 run's share of energy at wavelengths below 4 nodes (the paper:
-    "highly unstable" against "slightly unstable"); at 1800 / 2078 the LBGK
+    zeta-4 run's share of energy at wavelengths below 4 nodes (the paper
+    finds the first run far less stable than the second); at 1800 / 2078 the LBGK
     field is noise while the zeta-4 run still holds its vortices (finite,
     grid-scale share under 1 %, speeds of order u0)."""
     w3 = 1.99880
