@@ -14,9 +14,10 @@
 //    the taps mirrored and the transposed weights; the ReLU derivative is
 //    applied in its epilogue.
 //  * Weight gradient: a workgroup stages, row by row, the dZ row and the
-//    three input rows it needs in LDS channel-major (transposed), and each
-//    wave accumulates 32 x 32 x (64 nodes) MFMA products for its taps; block
-//    partials are summed in a fixed order (deterministic).
+//    three input rows it needs in LDS node-major and reads MFMA operands
+//    with transposing LDS reads; each wave accumulates 32 x 32 x (64 nodes)
+//    MFMA products for its taps; block partials are summed in a fixed order
+//    (deterministic).
 //  * Projection, loss and apply are per-node kernels: the projection removes
 //    the correction's mass, momentum and energy (the invariants of the
 //    collision), orthogonally in the metric of the output scales, so an
@@ -26,6 +27,9 @@
 //    the same streaming followed by the projection.  Apply hands those
 //    moments to the next step as a shift of the equilibrium, so the corrected
 //    node keeps the plain step's non-equilibrium part.
+//  * Training through corrected coarse steps: FP64 adjoints (vector-Jacobian
+//    products) of the fused step, the apply and the rollout loss, as
+//    separate calls and fused into two node passes per corrected step.
 //  * The coarse lattice may hold FP32 or FP64 populations; the network reads
 //    and corrects either.
 #include <hip/hip_runtime.h>
@@ -121,34 +125,48 @@ __device__ __forceinline__ void project(float (&v)[CREAL], const ClNorm &nm)
 
 // ---------------------------------------------------------------------------
 // population buffer (row layout (y*25 + k)*nx + x, FP32 or FP64) -> normalised
-// NHWC bf16; the difference from the mean is taken in the buffer's precision
+// NHWC bf16; the difference from the mean is taken in the buffer's precision.
+// A block takes 256 nodes of a row: thread t reads node t of each plane
+// (coalesced), packs channel pairs into LDS rows of 17 words (a stride
+// coprime with the 64 banks), and the block then stores the 256 x 64 bytes
+// as consecutive 16-byte chunks, one per lane.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_cl_input(PtrList post, int nx, int ny, ClNorm nm,
                                                   const float *__restrict__ noise, float amp,
                                                   u16 *__restrict__ x0)
 {
+    __shared__ uint32_t tile[256][17];
     const int f = blockIdx.z;
     const int y = blockIdx.y;
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= nx) return;
-    const T *P = static_cast<const T *>(post.p[f]);
-    const size_t node = ((size_t)f * ny + y) * nx + x;
-    float v[CH];
+    const int xb = blockIdx.x * 256;
+    const int x = xb + threadIdx.x;
+    if (x < nx) {
+        const T *P = static_cast<const T *>(post.p[f]);
+        float v[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        v[c] = 0.f;
-        if (c < CREAL) {
-            v[c] = (float)(P[((size_t)y * CREAL + c) * nx + x] - (T)nm.in_mean[c]) * nm.in_inv[c];
-            if (noise) v[c] += amp * noise[(((size_t)f * CREAL + c) * ny + y) * nx + x];
+        for (int c = 0; c < CH; ++c) {
+            v[c] = 0.f;
+            if (c < CREAL) {
+                v[c] = (float)(P[((size_t)y * CREAL + c) * nx + x] - (T)nm.in_mean[c]) * nm.in_inv[c];
+                if (noise) v[c] += amp * noise[(((size_t)f * CREAL + c) * ny + y) * nx + x];
+            }
         }
+#pragma unroll
+        for (int c = 0; c < CH; c += 2)
+            tile[threadIdx.x][c / 2] = (uint32_t)bf16_bits(v[c]) | ((uint32_t)bf16_bits(v[c + 1]) << 16);
     }
-    uint32_t w[CH / 2];
+    __syncthreads();
+    const int nodes = min(256, nx - xb);
+    u16 *dst = x0 + (((size_t)f * ny + y) * nx + xb) * CH;
 #pragma unroll
-    for (int c = 0; c < CH; c += 2) w[c / 2] = (uint32_t)bf16_bits(v[c]) | ((uint32_t)bf16_bits(v[c + 1]) << 16);
-    uint4 *dst = reinterpret_cast<uint4 *>(x0 + node * CH);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    for (int r = 0; r < 4; ++r) {
+        const int i = r * 256 + threadIdx.x;          // 16-byte chunk: node i / 4, quarter i % 4
+        const int n = i >> 2, q = i & 3;
+        if (n < nodes)
+            reinterpret_cast<uint4 *>(dst)[i] =
+                make_uint4(tile[n][4 * q], tile[n][4 * q + 1], tile[n][4 * q + 2], tile[n][4 * q + 3]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -561,33 +579,48 @@ __global__ __launch_bounds__(256) void k_cl_mgrad(const float *__restrict__ A, c
                                                   int nx, int ny, ClNorm nm, float reg2n,
                                                   u16 *__restrict__ dy3)
 {
+    // the node's bf16 row goes through LDS, so that the block's 256 x 64
+    // bytes are stored as consecutive 16-byte chunks (as in k_cl_input)
+    __shared__ uint32_t tile[256][17];
     const int f = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= nx) return;
-    const size_t plane = (size_t)nx * ny;
-    const size_t node = ((size_t)f * ny + y) * nx + x;
-    float t[CREAL];
+    const int xb = blockIdx.x * 256;
+    const int x = xb + threadIdx.x;
+    if (x < nx) {
+        const size_t plane = (size_t)nx * ny;
+        const size_t node = ((size_t)f * ny + y) * nx + x;
+        float t[CREAL];
 #pragma unroll
-    for (int k = 0; k < CREAL; ++k) {
-        int xs = x + nm.ivx[k], ys = y + nm.ivy[k];
-        xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
-        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
-        const float4 a = reinterpret_cast<const float4 *>(A)[(size_t)f * plane + (size_t)ys * nx + xs];
-        const float vx = nm.vx[k], vy = nm.vy[k];
-        t[k] = nm.out_scale[k] * (a.x + vx * a.y + vy * a.z + (vx * vx + vy * vy) * a.w) +
-               reg2n * y3[node * CH + k];
+        for (int k = 0; k < CREAL; ++k) {
+            int xs = x + nm.ivx[k], ys = y + nm.ivy[k];
+            xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+            ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
+            const float4 a = reinterpret_cast<const float4 *>(A)[(size_t)f * plane + (size_t)ys * nx + xs];
+            const float vx = nm.vx[k], vy = nm.vy[k];
+            t[k] = nm.out_scale[k] * (a.x + vx * a.y + vy * a.z + (vx * vx + vy * vy) * a.w);
+        }
+        if (reg2n != 0.f) {                           // the minimum-norm term, when asked for
+#pragma unroll
+            for (int k = 0; k < CREAL; ++k) t[k] += reg2n * y3[node * CH + k];
+        }
+        project(t, nm);
+#pragma unroll
+        for (int c = 0; c < CH; c += 2) {
+            const float a = c < CREAL ? t[c] : 0.f;
+            const float b = c + 1 < CREAL ? t[c + 1] : 0.f;
+            tile[threadIdx.x][c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+        }
     }
-    project(t, nm);
-    uint32_t w[CH / 2];
+    __syncthreads();
+    const int nodes = min(256, nx - xb);
+    u16 *dst = dy3 + (((size_t)f * ny + y) * nx + xb) * CH;
 #pragma unroll
-    for (int c = 0; c < CH; c += 2) {
-        const float a = c < CREAL ? t[c] : 0.f;
-        const float b = c + 1 < CREAL ? t[c + 1] : 0.f;
-        w[c / 2] = (uint32_t)bf16_bits(a) | ((uint32_t)bf16_bits(b) << 16);
+    for (int r = 0; r < 4; ++r) {
+        const int i = r * 256 + threadIdx.x;
+        const int n = i >> 2, q = i & 3;
+        if (n < nodes)
+            reinterpret_cast<uint4 *>(dst)[i] =
+                make_uint4(tile[n][4 * q], tile[n][4 * q + 1], tile[n][4 * q + 2], tile[n][4 * q + 3]);
     }
-    uint4 *dst = reinterpret_cast<uint4 *>(dy3 + (((size_t)f * ny + y) * nx + x) * CH);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) dst[c] = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
 }
 
 // Increment error d = (cons(truth_now) - cons(truth_prev)) - (cons(model_now)
