@@ -570,10 +570,9 @@ int plbm_closure_rollout_vjp(plbm_closure *c, const plbm_desc *coarse, const flo
  * output (FP32 NHWC x 32), 4..6 gradients w.r.t. layer-3/2/1 outputs,
  * 7 the physical correction c (FP32 planes [frame][k][y][x]),
  * 8 dL/dm (FP32 [frame][y][x][j], j = mass, x and y momentum, energy),
- * 9 the equilibrium shift of the last apply (FP64 planes [frame][k][y][x],
- * population k of node x), 10 per-node moment cotangents of the last
- * adjoint call (FP64 [frame][y][x][j]), 11 the gradient of the network
- * input (FP32 NHWC x 32). */
+ * 10 per-node moment cotangents of the last adjoint call (FP64
+ * [frame][y][x][j]), 11 the gradient of the network input (FP32 NHWC x 32).
+ * 9 is not a buffer (apply adds its equilibrium shift in place): PLBM_EINVAL. */
 int plbm_closure_activation(const plbm_closure *c, int which, const void **ptr, size_t *bytes);
 
 /*

@@ -162,15 +162,14 @@ class Closure:
     def activation(self, which):
         """Copy of an internal buffer: bf16 NHWC (which 0..2, 4..6) as float32
         (frames, ny, nx, 32), the FP32 output (3), the physical correction
-        (7: frames, 25, ny, nx), dL/dm (8: frames, 4, ny, nx), the last
-        equilibrium shift (9: frames, 25, ny, nx), the moment cotangents of the
-        last adjoint call (10: frames, 4, ny, nx) or the gradient of the
-        network input (11: frames, ny, nx, 32)."""
+        (7: frames, 25, ny, nx), dL/dm (8: frames, 4, ny, nx), the moment
+        cotangents of the last adjoint call (10: frames, 4, ny, nx) or the
+        gradient of the network input (11: frames, ny, nx, 32)."""
         ptr, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
         _plbm.check(_plbm.lib.plbm_closure_activation(self.handle, int(which), ctypes.byref(ptr),
                                                       ctypes.byref(nbytes)), "activation")
         nodes = self.frames * self.ny * self.nx
-        if which in (9, 10):
+        if which == 10:
             out = torch.empty(nbytes.value // 8, dtype=torch.float64, device=self.device)
         elif which in (3, 7, 8, 11):
             out = torch.empty(nbytes.value // 4, dtype=torch.float32, device=self.device)
@@ -179,7 +178,7 @@ class Closure:
         _plbm.check(_plbm.lib.plbm_stream_copy(ptr, ctypes.c_void_p(out.data_ptr()), nbytes.value,
                                                _stream(self.device)), "copy")
         nf = max(self._nf, 1)
-        if which in (7, 9):
+        if which == 7:
             return out.reshape(self.frames, 25, self.ny, self.nx)[:nf]
         if which in (8, 10):
             return out.reshape(self.frames, self.ny, self.nx, 4).permute(0, 3, 1, 2)[:nf]

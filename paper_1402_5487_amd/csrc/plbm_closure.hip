@@ -658,16 +658,17 @@ __global__ __launch_bounds__(256) void k_cl_target(Fields16 F, size_t n, float *
 // densities; they are given to the populations f = pull(P) of the next step
 // as  f <- f + f_eq(m + g) - f_eq(m)  (m the node's own moments), so the
 // node's moments become m + g exactly and its non-equilibrium part f - f_eq
-// is the plain step's.  In the pull layout the shift of population k at
-// node x is stored at x - v_k.
+// is the plain step's.  In the pull layout population k of node x is stored
+// at x - v_k.
 //
 // 1. k_cl_corr_apply: c = s * Ph y where every normalised component is
 //    finite and within bound, else c = 0 (fallback, counted in *skipped);
 // 2. k_cl_shift: per node, m from the pulled populations (FP64), g from c,
 //    delta = f_eq(m + g) - f_eq(m) (zero if the shifted density or
-//    temperature would not be positive);
-// 3. k_cl_scatter: P_k(x) += delta_k(x + v_k) in the storage type (delta is
-//    kept in FP64, so FP64 lattices conserve the totals to FP64 rounding).
+//    temperature would not be positive), added in place to the populations
+//    it pulled: the slot of population k at x - v_k is read and written by
+//    node x alone, so no other thread touches it.  The sum is rounded once
+//    to the storage type (FP64 lattices conserve the totals to FP64 rounding).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_cl_corr_apply(const float *__restrict__ y3, int nx, int ny, ClNorm nm,
                                                        float bound, float *__restrict__ C,
@@ -693,7 +694,7 @@ __global__ __launch_bounds__(256) void k_cl_corr_apply(const float *__restrict__
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__restrict__ C, int nx, int ny,
-                                                  ClNorm nm, KParams kp, double *__restrict__ delta)
+                                                  ClNorm nm, KParams kp)
 {
     // no fused multiply-adds: the two equilibria below are evaluated by the
     // same rounded operations, so a zero moment change gives a zero shift
@@ -702,7 +703,7 @@ __global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__r
     const int x = blockIdx.x * 256 + threadIdx.x;
     if (x >= nx) return;
     const size_t plane = (size_t)nx * ny;
-    const T *P = static_cast<const T *>(post.p[f]);
+    T *P = static_cast<T *>(post.p[f]);
     double fp[NQ];
     double g[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -727,6 +728,7 @@ __global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__r
     const double ux1 = (jx + g[1]) / r1, uy1 = (jy + g[2]) / r1;
     const double th1 = 0.5 * ((e + g[3]) / r1 - ux1 * ux1 - uy1 * uy1);
     const bool ok = r1 > 0.0 && th1 > 0.0 && isfinite(th1) && isfinite(ux1) && isfinite(uy1);
+    if (!ok) return;                                  // the node keeps its populations
     double a0[Q], b0[Q], a1[Q], b1[Q];
     rule1d<Fp64Math>(ux0, th0, kp, a0);
     rule1d<Fp64Math>(uy0, th0, kp, b0);
@@ -736,27 +738,13 @@ __global__ __launch_bounds__(256) void k_cl_shift(PtrList post, const float *__r
     for (int j = 0; j < Q; ++j)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
+            const int k = i + Q * j;
+            int xs = x - nm.ivx[k], ys = y - nm.ivy[k];
+            xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+            ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
             const double dlt = r1 * a1[i] * b1[j] - rho * a0[i] * b0[j];
-            delta[((size_t)f * CREAL + i + Q * j) * plane + (size_t)y * nx + x] = ok ? dlt : 0.0;
+            P[((size_t)ys * CREAL + k) * nx + xs] = (T)fp[k] + (T)dlt;
         }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_cl_scatter(PtrList post, const double *__restrict__ delta, int nx,
-                                                    int ny, ClNorm nm)
-{
-    const int f = blockIdx.z, y = blockIdx.y;
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x >= nx) return;
-    const size_t plane = (size_t)nx * ny;
-    T *P = static_cast<T *>(post.p[f]);
-#pragma unroll
-    for (int k = 0; k < CREAL; ++k) {
-        int xs = x + nm.ivx[k], ys = y + nm.ivy[k];
-        xs += xs < 0 ? nx : (xs >= nx ? -nx : 0);
-        ys += ys < 0 ? ny : (ys >= ny ? -ny : 0);
-        P[((size_t)y * CREAL + k) * nx + x] += (T)delta[((size_t)f * CREAL + k) * plane + (size_t)ys * nx + xs];
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1232,7 +1220,6 @@ struct plbm_closure {
     float *lpart = nullptr;                    // loss partials
     float *corr = nullptr;                     // c = s * Ph y, planes [f][k][y][x]
     float *mres = nullptr;                     // (2/N) w r, [f][y][x][j]
-    double *shift = nullptr;                   // equilibrium shift, planes [f][k][y][x]
     double *adj4 = nullptr;                    // per-node moment cotangents (adjoints), [f][y][x][j]
     float *dx = nullptr;                       // gradient of the network input, NHWC x 32
     double *lpart64 = nullptr;                 // rollout-loss partials
@@ -1391,7 +1378,6 @@ extern "C" int plbm_closure_create(const plbm_desc *coarse, int frames, plbm_clo
               hipMalloc((void **)&c->slices, (size_t)WR_SLICES * LAYER_P * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->corr, nodes * CREAL * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->mres, nodes * 4 * sizeof(float)) == hipSuccess &&
-              hipMalloc((void **)&c->shift, nodes * CREAL * sizeof(double)) == hipSuccess &&
               hipMalloc((void **)&c->adj4, nodes * 4 * sizeof(double)) == hipSuccess &&
               hipMalloc((void **)&c->dx, nodes * CH * sizeof(float)) == hipSuccess &&
               hipMalloc((void **)&c->lpart64, (size_t)c->nlblk * sizeof(double)) == hipSuccess;
@@ -1408,7 +1394,7 @@ extern "C" int plbm_closure_destroy(plbm_closure *c)
     if (!c) return PLBM_EINVAL;
     (void)hipDeviceSynchronize();
     void *ptrs[] = {c->wf, c->wt, c->x0, c->a1, c->a2, c->y3, c->dy3, c->dz2, c->dz1, c->part,
-                    c->lpart, c->corr, c->mres, c->shift, c->slices, c->adj4, c->dx, c->lpart64};
+                    c->lpart, c->corr, c->mres, c->slices, c->adj4, c->dx, c->lpart64};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -1528,15 +1514,10 @@ extern "C" int plbm_closure_apply(plbm_closure *c, void *const *post, int frames
     (void)hipGetLastError();
     const dim3 gn((c->nx + 255) / 256, c->ny, frames);
     hipLaunchKernelGGL(k_cl_corr_apply, gn, dim3(256), 0, st, c->y3, c->nx, c->ny, c->nm, bound, c->corr, skipped);
-    if (c->f64) {
-        hipLaunchKernelGGL(k_cl_shift<double>, gn, dim3(256), 0, st, pl, c->corr, c->nx, c->ny, c->nm, c->kp,
-                           c->shift);
-        hipLaunchKernelGGL(k_cl_scatter<double>, gn, dim3(256), 0, st, pl, c->shift, c->nx, c->ny, c->nm);
-    } else {
-        hipLaunchKernelGGL(k_cl_shift<float>, gn, dim3(256), 0, st, pl, c->corr, c->nx, c->ny, c->nm, c->kp,
-                           c->shift);
-        hipLaunchKernelGGL(k_cl_scatter<float>, gn, dim3(256), 0, st, pl, c->shift, c->nx, c->ny, c->nm);
-    }
+    if (c->f64)
+        hipLaunchKernelGGL(k_cl_shift<double>, gn, dim3(256), 0, st, pl, c->corr, c->nx, c->ny, c->nm, c->kp);
+    else
+        hipLaunchKernelGGL(k_cl_shift<float>, gn, dim3(256), 0, st, pl, c->corr, c->nx, c->ny, c->nm, c->kp);
     return ck(hipGetLastError());
 }
 
@@ -1742,7 +1723,6 @@ extern "C" int plbm_closure_activation(const plbm_closure *c, int which, const v
     case 6: p = c->dz1; break;
     case 7: p = c->corr; b = nodes * CREAL * sizeof(float); break;
     case 8: p = c->mres; b = nodes * 4 * sizeof(float); break;
-    case 9: p = c->shift; b = nodes * CREAL * sizeof(double); break;
     case 10: p = c->adj4; b = nodes * 4 * sizeof(double); break;
     case 11: p = c->dx; b = nodes * CH * sizeof(float); break;
     default: return PLBM_EINVAL;
