@@ -217,6 +217,25 @@ int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps,
               double *sums, void *stream);
 
 /*
+ * plbm_step_fields -- plbm_step (without sums) whose first step also writes
+ * the fields (rho, u_x, u_y, theta) of the state it reads, i.e. of the
+ * state at the start of the call (Sec. 2: rho = sum f, rho u = sum f v,
+ * 2 rho theta = sum f |v - u|^2 of the pulled populations, as
+ * plbm_moments reports them).  They are the moments the collision itself
+ * uses, so they cost no extra read: with FP64 storage they equal
+ * plbm_moments bit for bit; with FP32 or 16-bit storage they are taken in
+ * the step's FP32 arithmetic (plbm_moments sums in FP64).
+ *   f_a, f_b, nsteps : as plbm_step, nsteps >= 1
+ *   rho, ux, uy, theta : device FP64 planes of nx * ny values, row-major
+ *              (ny, nx); any may be NULL (not written)
+ * D2Q25 with the symmetric five-velocity set (dim 2) only; other
+ * descriptors return PLBM_EUNSUPPORTED.  Launches kernels only (no
+ * allocation or synchronisation).
+ */
+int plbm_step_fields(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *rho,
+                     double *ux, double *uy, double *theta, void *stream);
+
+/*
  * plbm_step_noalloc -- plbm_step without any device allocation, for callers
  * that cannot allocate device memory (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc).  Same arguments, results and

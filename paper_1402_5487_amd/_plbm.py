@@ -83,6 +83,7 @@ def _load():
     lib.plbm_init.argtypes = [P, vp, vp, vp, vp, vp, vp]
     lib.plbm_step.argtypes = [P, vp, vp, ctypes.c_int, D, vp]
     lib.plbm_step_noalloc.argtypes = [P, vp, vp, ctypes.c_int, D, vp]
+    lib.plbm_step_fields.argtypes = [P, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp]
     lib.plbm_moments.argtypes = [P, vp, vp, vp, vp, vp, D, vp]
     lib.plbm_dev_scales.argtypes = [P, vp, vp, vp, vp, vp]
     lib.plbm_init3.argtypes = [P, vp, vp, vp, vp, vp, vp, vp]
@@ -101,7 +102,8 @@ lib = _load()
 EXPORTED = ("plbm_coeffs", "plbm_desc_default", "plbm_buffer_elems",
             "plbm_elem_bytes", "plbm_init", "plbm_step", "plbm_moments",
             "plbm_dev_scales", "plbm_strerror", "plbm_last_hip_error",
-            "plbm_stream_copy", "plbm_init3", "plbm_moments3", "plbm_step_noalloc")
+            "plbm_stream_copy", "plbm_init3", "plbm_moments3", "plbm_step_noalloc",
+            "plbm_step_fields")
 
 
 def strerror(status):
@@ -204,6 +206,13 @@ def step(d, fa, fb, nsteps, want_sums, stream):
     check(lib.plbm_step(ctypes.byref(d), _ptr(fa), _ptr(fb), int(nsteps), sums,
                         _stream(stream)), "plbm_step")
     return list(sums) if want_sums else None
+
+
+def step_fields(d, fa, fb, nsteps, rho, ux, uy, theta, stream):
+    """plbm_step_fields: nsteps steps, the first also writing the fields
+    of the state it reads into the given FP64 device tensors (or None)."""
+    check(lib.plbm_step_fields(ctypes.byref(d), _ptr(fa), _ptr(fb), int(nsteps), _ptr(rho), _ptr(ux),
+                               _ptr(uy), _ptr(theta), _stream(stream)), "plbm_step_fields")
 
 
 def step_noalloc(d, fa, fb, nsteps, want_sums, stream):

@@ -256,11 +256,21 @@ class Experiment:
         rng.shuffle(order)
         nxt = [0]
 
+        # The fine run is kept one coarse step ahead: each of its
+        # step_fields(factor) calls also returns the fields of the state it
+        # starts from (no separate moments pass), which is the truth at the
+        # coarse time the corrected run has just reached.
+        nf = self.nf
+        fbuf = tuple(torch.empty((nf, nf), dtype=torch.float64, device=self.device) for _ in range(4))
+
+        def truth_of(fine):
+            return restrict(*fine.step_fields(self.factor, out=fbuf), self.factor)
+
         def fresh():
             s = order[nxt[0] % len(order)]
             nxt[0] += 1
             fine = self.fine_lattice(s)
-            return [fine, self.coarse_lattice().init(*self.restricted(fine)), 0]
+            return [fine, self.coarse_lattice().init(*truth_of(fine)), 0]
 
         runs = [fresh() for _ in range(B)]
         nbuf = nc * nc * 25
@@ -273,13 +283,12 @@ class Experiment:
             pre, truth = [], []
             for _ in range(seg):
                 for r in runs:
-                    r[0].step(self.factor)
                     r[1].step(1)
                 pre.append([r[1].f.clone() for r in runs])
                 self.net.forward(p, [r[1].f for r in runs])
                 self.net.apply([r[1].f for r in runs], bound=float("inf"))
                 post.append([r[1].f.clone() for r in runs])
-                truth.append([self.restricted(r[0]) for r in runs])
+                truth.append([truth_of(r[0]) for r in runs])
             # backward through the segment (one fused call per step; the
             # segment loss stays on the device until the last)
             desc = runs[0][1].desc

@@ -325,9 +325,10 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // In place: f <- (1 - omega) f + omega f_eq (Eq. srt, collision half), with
-// f_eq = rho r^x_i r^y_j (tensor product, Eq. eqdist).
+// f_eq = rho r^x_i r^y_j (tensor product, Eq. eqdist).  mom receives the
+// node's (rho, u_x, u_y, theta) before the collision.
 template <class S>
-__device__ __forceinline__ void collide2d(typename S::C (&f)[NQ], const KParams &p)
+__device__ __forceinline__ void collide2d(typename S::C (&f)[NQ], const KParams &p, typename S::C (&mom)[4])
 {
     using C = typename S::C;
     C rho, jx, jy, e;
@@ -335,6 +336,10 @@ __device__ __forceinline__ void collide2d(typename S::C (&f)[NQ], const KParams 
     const C inv = recip(rho);
     const C ux = jx * inv, uy = jy * inv;
     const C theta = C(0.5) * (e * inv - ux * ux - uy * uy);
+    mom[0] = rho;
+    mom[1] = ux;
+    mom[2] = uy;
+    mom[3] = theta;
     C rx[Q], ry[Q];
     rule1d<S>(ux, theta, p, rx);
     rule1d<S>(uy, theta, p, ry);
@@ -348,6 +353,19 @@ __device__ __forceinline__ void collide2d(typename S::C (&f)[NQ], const KParams 
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i + Q * j] = fma(keep, f[i + Q * j], rx[i] * ry[j]);
 }
+
+template <class S>
+__device__ __forceinline__ void collide2d(typename S::C (&f)[NQ], const KParams &p)
+{
+    typename S::C mom[4];
+    collide2d<S>(f, p, mom);
+}
+
+// Optional per-node outputs of a step: (rho, u_x, u_y, theta) planes of the
+// state it reads, row-major (ny, nx); a NULL plane is not written.
+struct FieldsOut {
+    double *p[4];
+};
 
 // ---------------------------------------------------------------------------
 // Reductions (FP64): wave64 butterfly, then LDS across the block's waves.
@@ -557,11 +575,11 @@ __device__ __forceinline__ void accumulate_sums(const typename S::C (&f)[NQ], co
 // + (vector offset).  With paired nodes (NV = 2) the waves whose windows
 // cross the periodic seam in x or the ragged right edge take a per-node path
 // with wrapped indices instead.
-template <class S, int NV, bool SUMS>
+template <class S, int NV, bool SUMS, bool FIELDS = false>
 __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
                                           typename S::T *__restrict__ dst, const KParams &p,
                                           int xb, int y_first, int y_step, int nrows,
-                                          double (&acc)[4])
+                                          double (&acc)[4], const FieldsOut &fo = FieldsOut{})
 {
     using T = typename S::T;
     using C = typename S::C;
@@ -667,7 +685,18 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
             C f[NQ];
 #pragma unroll
             for (int k = 0; k < NQ; ++k) f[k] = S::dec(L::get(raw[k], m), k, p);
-            collide2d<S>(f, p);
+            if constexpr (FIELDS) {
+                C mom[4];
+                collide2d<S>(f, p, mom);
+                if (full || xb + m < nx) {
+                    const long long n = (long long)y * nx + (xb + m);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (fo.p[q]) fo.p[q][n] = (double)mom[q];
+                }
+            } else {
+                collide2d<S>(f, p);
+            }
             const uint32_t salt = S::key((uint32_t)y * (uint32_t)nx + (uint32_t)(xb + m));   // the node
 #pragma unroll
             for (int k = 0; k < NQ; ++k) out[k][m] = S::enc(f[k], k, p, salt);
@@ -704,14 +733,14 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
 }
 
 // One tile of the single-lattice launch: TX * NV nodes of each of TY rows.
-template <class S, int NV, bool SUMS>
+template <class S, int NV, bool SUMS, bool FIELDS = false>
 __device__ __forceinline__ void step_tile(const typename S::T *__restrict__ src,
                                           typename S::T *__restrict__ dst, const KParams &p,
-                                          int tile, double (&acc)[4])
+                                          int tile, double (&acc)[4], const FieldsOut &fo = FieldsOut{})
 {
     const int tyi = tile / p.tiles_x, txi = tile - tyi * p.tiles_x;
     const int xb = txi * (TX * NV) + threadIdx.x * NV;
-    step_rows<S, NV, SUMS>(src, dst, p, xb, tyi * TY, 1, TY, acc);
+    step_rows<S, NV, SUMS, FIELDS>(src, dst, p, xb, tyi * TY, 1, TY, acc, fo);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,6 +73,20 @@ __global__ __launch_bounds__(TX, PLBM_MIN_WAVES) void k_step2d(const typename S:
     if constexpr (SUMS) block_sums_store<4>(acc, partials + (size_t)blockIdx.x * 4);
 }
 
+// The same step, also writing the pre-collision fields of the state it reads
+// (the moments its collision uses, in its arithmetic).
+template <class S, int NV>
+__global__ __launch_bounds__(TX, PLBM_MIN_WAVES) void k_step2d_fields(const typename S::T *__restrict__ src,
+                                                                      typename S::T *__restrict__ dst,
+                                                                      KParams p, FieldsOut fo)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int slot = xcd_tile(blockIdx.x, gridDim.x);
+#pragma unroll 1
+    for (int tile = slot; tile < p.ntiles; tile += gridDim.x)
+        step_tile<S, NV, false, true>(src, dst, p, tile, acc, fo);
+}
+
 // ---------------------------------------------------------------------------
 // 2D initialisation: the buffer whose pull is f_eq.  Node x computes its own
 // equilibrium and scatters population k to x - v_k, so that pulling it back
@@ -389,6 +403,30 @@ int launch_step(const KParams &p, const plbm_desc *d, const void *src, void *dst
     return launch_status();
 }
 
+// 2D steps of which the first also writes the fields of the state it reads.
+template <class S>
+int run_steps_fields(const KParams &p, const plbm_desc *d, void *fa, void *fb, int nsteps, FieldsOut fo,
+                     hipStream_t st)
+{
+    using T = typename S::T;
+    clear_launch_error();
+    const int nblocks = grid_for(p.ntiles);
+    const size_t lds = sizeof(T) == 2 ? (d->rounding == PLBM_ROUND_STOCHASTIC ? PLBM_LDS_CAP_16SR
+                                                                             : PLBM_LDS_CAP_16)
+                                      : PLBM_LDS_CAP_WIDE;
+    if (p.nv == 2)
+        hipLaunchKernelGGL((k_step2d_fields<S, 2>), dim3(nblocks), dim3(TX), lds, st, (const T *)fa, (T *)fb, p,
+                           fo);
+    else
+        hipLaunchKernelGGL((k_step2d_fields<S, 1>), dim3(nblocks), dim3(TX), lds, st, (const T *)fa, (T *)fb, p,
+                           fo);
+    int rc = launch_status();
+    int nb = 0;
+    for (int s = 1; s < nsteps && rc == PLBM_OK; ++s)
+        rc = launch_step<S, false>(p, d, (s & 1) ? fb : fa, (s & 1) ? fa : fb, nullptr, st, nb);
+    return rc;
+}
+
 // `scratch`: NULL, or a device buffer of (NOALLOC_BLOCKS + 1) * 4 doubles
 // that receives the partial sums instead of a stream-ordered allocation (the
 // sums launch then runs at most NOALLOC_BLOCKS workgroups).
@@ -480,6 +518,12 @@ int step_dispatch(const KParams &p, const plbm_desc *d, void *fa, void *fb, int 
     PLBM_DISPATCH(d, run_steps, p, d, fa, fb, n, sums, st, scratch);
 }
 
+int step_fields_dispatch(const KParams &p, const plbm_desc *d, void *fa, void *fb, int n, FieldsOut fo,
+                         hipStream_t st)
+{
+    PLBM_DISPATCH(d, run_steps_fields, p, d, fa, fb, n, fo, st);
+}
+
 int moments_dispatch(const KParams &p, const plbm_desc *d, const void *f, double *rho, double *ux,
                      double *uy, double *th, double *part, hipStream_t st, int &nb,
                      int max_blocks = MAX_GRID)
@@ -537,6 +581,19 @@ extern "C" int plbm_step(const plbm_desc *d, void *f_a, void *f_b, int nsteps, d
         return PLBM_OK;
     }
     return step_dispatch(p, d, f_a, f_b, nsteps, sums, as_stream(stream));
+}
+
+extern "C" int plbm_step_fields(const plbm_desc *d, void *f_a, void *f_b, int nsteps, double *rho, double *ux,
+                                double *uy, double *theta, void *stream)
+{
+    if (!d) return PLBM_EINVAL;
+    if (d->dim != 2 || plbm::gen_handles(d) || d->q1d != Q) return PLBM_EUNSUPPORTED;
+    KParams p;
+    int rc = make_params(d, p);
+    if (rc != PLBM_OK) return rc;
+    if (!f_a || !f_b || f_a == f_b || nsteps < 1) return PLBM_EINVAL;
+    FieldsOut fo = {{rho, ux, uy, theta}};
+    return step_fields_dispatch(p, d, f_a, f_b, nsteps, fo, as_stream(stream));
 }
 
 namespace {

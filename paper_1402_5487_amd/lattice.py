@@ -94,6 +94,20 @@ class Lattice:
         self.t += nsteps
         return out
 
+    def step_fields(self, nsteps=1, out=None):
+        """nsteps steps (2D D2Q25), the first also writing (rho, ux, uy, theta)
+        of the state it reads, i.e. moments() before the call, at no extra
+        read.  out: None or four float64 (ny, nx) device tensors."""
+        if out is None:
+            out = tuple(torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+                        for _ in range(4))
+        fa, fb = self.bufs[self.cur], self.bufs[1 - self.cur]
+        _plbm.step_fields(self.desc, fa, fb, nsteps, *out, self.stream)
+        if nsteps % 2 == 1:
+            self.cur = 1 - self.cur
+        self.t += nsteps
+        return tuple(out)
+
     def moments(self, sums=False):
         """(rho, ux, uy, theta) of the current pre-collision state as float64
         device tensors shaped (ny, nx) (1D: (nx,), uy None)."""

@@ -1,0 +1,65 @@
+"""plbm_step_fields: steps whose first also writes (rho, u, theta) of the
+state it reads, i.e. moments() before the call.
+
+With FP64 storage they are the moments the collision uses, computed by the
+same FP64 operations as plbm_moments, so they must equal it bit for bit;
+the populations the call leaves must equal plbm_step's bit for bit in every
+storage form.  FP32 and 16-bit storage take the fields in the step's FP32
+arithmetic: 25-term FP32 sums of values of size rho / 25, so within 32
+FP32 ulps of rho (2^-18) of the FP64 moments, scaled by the field (u by its
+floor U0, as in the parity tests)."""
+import pytest
+import torch
+
+from paper_1402_5487_amd import _plbm, inputs
+from paper_1402_5487_amd.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(300, 37), (256, 64), (1000, 9)]       # ragged row ends, several tiles
+
+
+def _lat(nx, ny, storage, seed=0):
+    fields = inputs.kelvin_helmholtz(nx, ny, u0=0.1, delta=max(ny / 20.0, 1.0), theta=0.35)
+    kw = dict(theta0=0.35) if storage.endswith("dev") else {}
+    lat = Lattice(2, nx, ny, omega=1.8, storage=storage, **kw).init(*fields)
+    lat.step(3 + seed)
+    return lat
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("nsteps", [1, 4])
+def test_fp64_fields_equal_moments_and_steps_equal_plain_steps(nx, ny, nsteps):
+    a, b = _lat(nx, ny, "f64"), _lat(nx, ny, "f64")
+    before = a.moments()
+    got = a.step_fields(nsteps)
+    b.step(nsteps)
+    for g, w in zip(got, before):
+        assert torch.equal(g, w)
+    assert torch.equal(a.f, b.f) and a.cur == b.cur and a.t == b.t
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev", "bf16dev"])
+def test_fields_in_the_step_arithmetic(storage):
+    a, b = _lat(300, 37, storage), _lat(300, 37, storage)
+    before = a.moments()
+    got = a.step_fields(2)
+    b.step(2)
+    assert torch.equal(a.f, b.f)
+    for g, w, floor in zip(got, before, (1.0, 0.1, 0.1, 1.0)):
+        scale = max(float(w.abs().max()), floor)
+        assert float((g - w).abs().max()) <= 2.0 ** -18 * scale, storage
+
+
+def test_null_planes_are_skipped_and_bad_calls_refused():
+    a = _lat(256, 16, "f64")
+    rho = torch.full((16, 256), -1.0, dtype=torch.float64, device="cuda")
+    want = a.moments()[0]
+    _plbm.step_fields(a.desc, a.f, a.bufs[1 - a.cur], 1, rho, None, None, None, a.stream)
+    assert torch.equal(rho, want)
+    with pytest.raises(_plbm.PlbmError):                      # nsteps must be >= 1
+        _plbm.step_fields(a.desc, a.f, a.bufs[1 - a.cur], 0, rho, None, None, None, a.stream)
+    one_d = Lattice(1, 64, omega=1.5)
+    with pytest.raises(_plbm.PlbmError):                      # 2D D2Q25 only
+        _plbm.step_fields(one_d.desc, one_d.f, one_d.bufs[1], 1, None, None, None, None,
+                          one_d.stream)
