@@ -315,10 +315,13 @@ def test_training_reduces_loss():
 
 
 def test_trained_closure_gains_on_held_out_steps():
-    """What the trained network gains over the plain coarse step: on frames
-    of held-out seeds, the share of the one-step error of the conserved
-    densities (against the restricted fine run) that the corrected step
-    removes."""
+    """The one-step training path (Experiment.train on one-step targets, the
+    library's plbm_closure_backward): on frames of held-out seeds, the share
+    of the one-step error of the conserved densities (against the restricted
+    fine run) that the corrected step removes.  This path learns single
+    steps but does not improve rollouts; the shipped closure is trained
+    through coarse steps and its rollout gain is asserted in
+    test_gpu_closure_rollout."""
     from paper_1402_5487_amd.closure_train import Experiment
     ex = Experiment(n_coarse=128, factor=4, batch=8)
     ex.generate(seeds=range(100, 102), per_seed=8, horizon=120, rng_seed=3)
