@@ -8,9 +8,9 @@ differences through the oracle's own moments and equilibrium, so no second
 copy of the equilibrium formula exists here.  The largest |eigenvalue| over a
 kappa grid tells whether round-off grows (> 1) or decays.
 
-The paper states only that omega = 1.9 is close to the upper limit for its
-thermal KH run (Sec. 4); the analysis makes that statement quantitative for
-any (theta, u, omega).
+For its thermal KH run the paper remarks only that omega = 1.9 lies near the
+largest stable value (Sec. 4); the analysis makes that quantitative for any
+(theta, u, omega).
 """
 import numpy as np
 
