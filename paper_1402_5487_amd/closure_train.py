@@ -234,7 +234,7 @@ class Experiment:
         return sig.tolist()
 
     def train_rollout(self, seeds, iters, seg=32, horizon=500, lr=2e-4, reg=0.0, seed=0,
-                      log=None):
+                      log=None, decay=None):
         """Adam on the rollout loss: `batch` corrected coarse runs, each
         beside its restricted fine run and started from the equilibrium of
         R_0, advance `seg` steps per iteration; the loss is the weighted mean
@@ -309,7 +309,10 @@ class Experiment:
                     loss = got
                 lam, tmp = tmp, lam
             if math.isfinite(loss):
-                self.net.adam(p, g, m, v, it, lr=lr * min(1.0, it / 50.0))
+                rate = lr * min(1.0, it / 50.0)
+                if decay is not None:           # cosine from lr to decay * lr over the iterations
+                    rate *= decay + (1.0 - decay) * 0.5 * (1.0 + math.cos(math.pi * it / iters))
+                self.net.adam(p, g, m, v, it, lr=rate)
             hist.append((it, loss))
             if log and (it % 50 == 0 or it == 1):
                 log(f"closure rollout training: iteration {it}, segment loss {loss:.4g}")
@@ -391,15 +394,16 @@ def forward_rate(ex, reps=20):
 
 
 def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 220),
-        iters=600, seg=32, batch=8, lr=2e-4, judge_steps=500, judge_every=50, storage="f32",
-        log=None):
+        iters=1200, seg=32, batch=8, lr=2e-4, judge_steps=500, judge_every=50, storage="f32",
+        log=None, decay=0.1):
     """The full learned-closure experiment: normalise, train through
     coarse steps, judge.
 
     Normalisation comes from one-step frames of 8 training seeds and the
     plain run's state errors on 4 of them.  The network starts from a zero
     output layer (the plain step) and is trained by train_rollout on the
-    training seeds; the fallback bound is calibrated on corrected rollouts of
+    training seeds, the learning rate decaying along a cosine from lr to
+    decay * lr; the fallback bound is calibrated on corrected rollouts of
     two training seeds.  The judge runs every held-out seed for judge_steps
     coarse steps from the equilibrium of R_0, plain and corrected, in the
     coarse storage of the experiment and, with the same network, in the
@@ -415,7 +419,7 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
     setup_s = time.perf_counter() - t0
     ex.params = init_params(0, ex.device, out_gain=0.0)
     t0 = time.perf_counter()
-    hist = ex.train_rollout(seeds, iters, seg=seg, lr=lr, log=say)
+    hist = ex.train_rollout(seeds, iters, seg=seg, lr=lr, log=say, decay=decay)
     train_s = time.perf_counter() - t0
     say(f"closure: trained {iters} rollout iterations of {seg} steps x {batch} runs in {train_s:.1f} s")
     # one-step skill on held-out frames (the moment loss of a single step)
@@ -430,7 +434,7 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
     out = {"coarse": n_coarse, "fine": n_coarse * factor, "omega_c": ex.omega_c,
            "storage": storage, "train_seeds": len(seeds), "held_out_seeds": len(list(held_seeds)),
            "training": "through coarse steps (adjoint of the step, apply and network)",
-           "iters": iters, "segment": seg, "batch": batch, "lr": lr,
+           "iters": iters, "segment": seg, "batch": batch, "lr": lr, "lr_decay_to": decay,
            "rollout_sigma": sigma, "setup_s": setup_s, "train_s": train_s,
            "ms_per_iter": 1e3 * train_s / iters,
            "loss_first_last": [hist[0][1], hist[-1][1]],
