@@ -275,7 +275,8 @@ def gen_forms(args):
 
 
 def accuracy(forms, n, fields, steps, theta):
-    """Max abs error of rho, u, theta against the FP64 form after `steps`."""
+    """Max abs error of rho, u, theta against the FP64 form after `steps`,
+    and the normwise relative errors ||m - m_ref||_2 / ||m_ref||_2."""
     import torch
     out, jobs = {}, {}
     ref = None
@@ -298,6 +299,8 @@ def accuracy(forms, n, fields, steps, theta):
                         "ux": float((mom[1] - ref[1]).abs().max()),
                         "uy": float((mom[2] - ref[2]).abs().max()),
                         "theta": float((mom[3] - ref[3]).abs().max()),
+                        "rel_l2": {k: float((a - b).norm() / b.norm())
+                                   for k, a, b in zip(("rho", "ux", "uy", "theta"), mom, ref)},
                         "finite": bool(torch.isfinite(mom[0]).all())}
         del mom
     return out, jobs
