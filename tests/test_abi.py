@@ -117,6 +117,27 @@ def test_step_noalloc_validates_before_launch():
     assert lib.plbm_step_noalloc(ctypes.byref(dg), a, b, 1, s, None) == _plbm.PLBM_EUNSUPPORTED
 
 
+def test_step_fields_and_rollout_vjp_validate_before_launch():
+    """plbm_step_fields takes D2Q25 only and at least one step; the fused
+    rollout adjoint refuses a missing closure or arrays before any device
+    call."""
+    lib = _plbm.lib
+    a, b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    d = _plbm.desc_default(2, 64, 64, 1.5, "f64")
+    assert lib.plbm_step_fields(ctypes.byref(d), a, b, 0, None, None, None, None, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step_fields(ctypes.byref(d), a, a, 1, None, None, None, None, None) == _plbm.PLBM_EINVAL
+    assert lib.plbm_step_fields(None, a, b, 1, None, None, None, None, None) == _plbm.PLBM_EINVAL
+    for other in (_plbm.desc_default(1, 64, 1, 1.0, "f64"), _plbm.desc_q3(2, 64, 64, 1.5, "f64", zeta=4.0),
+                  _plbm.desc_3d(16, 16, 16, 1.5, "f64"),
+                  _plbm.desc_general(2, 64, 64, 1.5, "f64", (0, 1, -1, 2, -3))):
+        assert lib.plbm_step_fields(ctypes.byref(other), a, b, 1, None, None, None, None,
+                                    None) == _plbm.PLBM_EUNSUPPORTED
+    p = ctypes.c_void_p(0x3000)
+    arr = (ctypes.c_void_p * 1)(0x4000)
+    assert lib.plbm_closure_rollout_vjp(None, ctypes.byref(d), p, 0.0, p, 0, arr, arr, 1.0, arr, None, None,
+                                        None, 1, None, None) == _plbm.PLBM_EINVAL
+
+
 def test_general_sets_are_validated_before_launch():
     """Asymmetric and q1d = 4, 6, 7 sets take the general kernels; what they
     cannot run is refused on the host: 16-bit storage, a table that is not
