@@ -79,7 +79,7 @@ def parse():
                     help="steps of the batching form (0 skips it)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batching form (for profilers)")
-    ap.add_argument("--closure-iters", type=int, default=1200,
+    ap.add_argument("--closure-iters", type=int, default=2000,
                     help="training iterations (segments of 32 coarse steps x 8 runs) of the "
                          "learned closure (0 skips it)")
     ap.add_argument("--closure-storage", default="f32", choices=("f32", "f64"),

@@ -234,7 +234,7 @@ class Experiment:
         return sig.tolist()
 
     def train_rollout(self, seeds, iters, seg=32, horizon=500, lr=2e-4, reg=0.0, seed=0,
-                      log=None, decay=None):
+                      log=None, decay=None, revisit=None):
         """Adam on the rollout loss: `batch` corrected coarse runs, each
         beside its restricted fine run and started from the equilibrium of
         R_0, advance `seg` steps per iteration; the loss is the weighted mean
@@ -242,7 +242,14 @@ class Experiment:
         its gradient comes back through every corrected step (adjoints of the
         apply, the network and the fused step; truncated at the segment
         start).  A run restarts on the next training seed after `horizon`
-        steps, or at once if its state stops being finite."""
+        steps, or at once if its state stops being finite.
+
+        The seeds are visited in a shuffled order.  With revisit = (block,
+        rounds) the order is cut into groups of `batch` seeds and every
+        `block` consecutive groups are visited `rounds` times in turn; a
+        seed's restricted fine trajectory is kept in device memory from its
+        first visit until its last, so the revisits run no fine steps (the
+        truth depends on the seed only, not on the network)."""
         from . import _plbm
         if self.params is None:
             self.params = init_params(seed, self.device)
@@ -254,7 +261,14 @@ class Experiment:
         order = list(seeds)
         rng = random.Random(seed)
         rng.shuffle(order)
+        if revisit is not None:
+            block, rounds = revisit
+            groups = [order[i:i + B] for i in range(0, len(order), B)]
+            order = [s_ for i in range(0, len(groups), block) for _ in range(rounds)
+                     for gr in groups[i:i + block] for s_ in gr]
         nxt = [0]
+        length = -(-horizon // seg) * seg          # steps a full visit runs
+        cache = {}                                 # seed -> [truth at t = 0, 1, ...] (complete only)
 
         # The fine run is kept one coarse step ahead: each of its
         # step_fields(factor) calls also returns the fields of the state it
@@ -267,12 +281,37 @@ class Experiment:
             return restrict(*fine.step_fields(self.factor, out=fbuf), self.factor)
 
         def fresh():
-            s = order[nxt[0] % len(order)]
+            """A run: [fine lattice or None, coarse lattice, steps, seed, truths, recording]."""
+            s_ = order[nxt[0] % len(order)]
             nxt[0] += 1
-            fine = self.fine_lattice(s)
-            return [fine, self.coarse_lattice().init(*truth_of(fine)), 0]
+            if s_ in cache:
+                truths = cache[s_]
+                return [None, self.coarse_lattice().init(*truths[0]), 0, s_, truths, False]
+            fine = self.fine_lattice(s_)
+            r0 = truth_of(fine)
+            return [fine, self.coarse_lattice().init(*r0), 0, s_, [r0], revisit is not None]
 
-        runs = [fresh() for _ in range(B)]
+        def next_truth(r):
+            t = r[2] + 1
+            if r[0] is None:
+                return r[4][t]
+            tr = truth_of(r[0])
+            if r[5]:
+                r[4].append(tr)
+            return tr
+
+        def finish(r):
+            """Keep a completed recording while the seed is due again soon."""
+            if r[5] and len(r[4]) == length + 1:
+                cache[r[3]] = r[4]
+            upcoming = [order[(nxt[0] + k) % len(order)] for k in range(B * (revisit[0] if revisit else 1))]
+            if r[3] in cache and r[3] not in upcoming and \
+                    all(q[3] != r[3] for q in runs if q is not None and q is not r):
+                del cache[r[3]]
+
+        runs = []
+        for _ in range(B):
+            runs.append(fresh())
         nbuf = nc * nc * 25
         lam = [torch.empty(nbuf, dtype=torch.float64, device=self.device) for _ in range(B)]
         tmp = [torch.empty_like(l) for l in lam]
@@ -281,14 +320,16 @@ class Experiment:
         for it in range(1, iters + 1):
             post = [[r[1].f.clone() for r in runs]]
             pre, truth = [], []
-            for _ in range(seg):
+            for step in range(seg):
                 for r in runs:
                     r[1].step(1)
                 pre.append([r[1].f.clone() for r in runs])
                 self.net.forward(p, [r[1].f for r in runs])
                 self.net.apply([r[1].f for r in runs], bound=float("inf"))
                 post.append([r[1].f.clone() for r in runs])
-                truth.append([truth_of(r[0]) for r in runs])
+                truth.append([next_truth(r) for r in runs])
+                for r in runs:
+                    r[2] += 1
             # backward through the segment (one fused call per step; the
             # segment loss stays on the device until the last)
             desc = runs[0][1].desc
@@ -317,11 +358,13 @@ class Experiment:
             if log and (it % 50 == 0 or it == 1):
                 log(f"closure rollout training: iteration {it}, segment loss {loss:.4g}")
             for b, r in enumerate(runs):
-                r[2] += seg
                 if r[2] >= horizon or not math.isfinite(loss) or \
                         not bool(torch.isfinite(post[-1][b][:1024]).all()):
+                    runs[b] = None
+                    finish(r)
                     runs[b] = fresh()
         torch.cuda.synchronize(self.device)
+        cache.clear()
         return hist
 
     # -- judging ---------------------------------------------------------
@@ -394,8 +437,8 @@ def forward_rate(ex, reps=20):
 
 
 def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 220),
-        iters=1200, seg=32, batch=8, lr=2e-4, judge_steps=500, judge_every=50, storage="f32",
-        log=None, decay=0.1):
+        iters=2000, seg=32, batch=8, lr=2e-4, judge_steps=500, judge_every=50, storage="f32",
+        log=None, decay=0.1, revisit=(3, 5)):
     """The full learned-closure experiment: normalise, train through
     coarse steps, judge.
 
@@ -403,7 +446,8 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
     plain run's state errors on 4 of them.  The network starts from a zero
     output layer (the plain step) and is trained by train_rollout on the
     training seeds, the learning rate decaying along a cosine from lr to
-    decay * lr; the fallback bound is calibrated on corrected rollouts of
+    decay * lr, each seed visited `rounds` times within a block of groups
+    with its fine trajectory kept between the visits (revisit); the fallback bound is calibrated on corrected rollouts of
     two training seeds.  The judge runs every held-out seed for judge_steps
     coarse steps from the equilibrium of R_0, plain and corrected, in the
     coarse storage of the experiment and, with the same network, in the
@@ -419,7 +463,7 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
     setup_s = time.perf_counter() - t0
     ex.params = init_params(0, ex.device, out_gain=0.0)
     t0 = time.perf_counter()
-    hist = ex.train_rollout(seeds, iters, seg=seg, lr=lr, log=say, decay=decay)
+    hist = ex.train_rollout(seeds, iters, seg=seg, lr=lr, log=say, decay=decay, revisit=revisit)
     train_s = time.perf_counter() - t0
     say(f"closure: trained {iters} rollout iterations of {seg} steps x {batch} runs in {train_s:.1f} s")
     # one-step skill on held-out frames (the moment loss of a single step)
@@ -435,6 +479,7 @@ def run(n_coarse=256, factor=4, train_seeds=range(200), held_seeds=range(200, 22
            "storage": storage, "train_seeds": len(seeds), "held_out_seeds": len(list(held_seeds)),
            "training": "through coarse steps (adjoint of the step, apply and network)",
            "iters": iters, "segment": seg, "batch": batch, "lr": lr, "lr_decay_to": decay,
+           "revisit": list(revisit) if revisit else None,
            "rollout_sigma": sigma, "setup_s": setup_s, "train_s": train_s,
            "ms_per_iter": 1e3 * train_s / iters,
            "loss_first_last": [hist[0][1], hist[-1][1]],

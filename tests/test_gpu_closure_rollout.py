@@ -4,8 +4,9 @@ rollouts it is judged by.
 The shipped configuration (closure_train.run defaults, as the benchmark runs
 it): a coarse 256^2 FP32 KH lattice beside its 1024^2 FP64 fine run, the
 network trained through segments of 32 corrected coarse steps (adjoints of
-the fused step, the apply and the network; 1200 iterations of 8 runs on the
-200 training seeds, the learning rate decaying along a cosine).  Judged on
+the fused step, the apply and the network; 2000 iterations of 8 runs on the
+200 training seeds, each seed visited five times with its fine trajectory
+kept between visits, the learning rate decaying along a cosine).  Judged on
 held-out seeds: relative L2 errors of rho, |u| and theta against the
 restricted fine run, averaged over 500 coarse steps, must be smaller with the
 closure than without, seed by seed, with FP32 and with FP64 coarse
