@@ -47,6 +47,22 @@ def coarse_omega(omega_f, factor):
     return 1.0 / (0.5 + (1.0 / omega_f - 0.5) / factor)
 
 
+def visit_order(seeds, batch, seed=0, revisit=None):
+    """The order in which rollout training's runs take the training seeds:
+    shuffled (random.Random(seed)); with revisit = (block, rounds), cut into
+    groups of `batch` and every `block` consecutive groups repeated
+    `rounds` times in turn (so a seed's visits fall within block * batch
+    consecutive visits of each other)."""
+    order = list(seeds)
+    random.Random(seed).shuffle(order)
+    if revisit is None:
+        return order
+    block, rounds = revisit
+    groups = [order[i:i + batch] for i in range(0, len(order), batch)]
+    return [s for i in range(0, len(groups), block) for _ in range(rounds)
+            for gr in groups[i:i + block] for s in gr]
+
+
 class Experiment:
     def __init__(self, n_coarse=256, factor=4, theta=0.35, omega_f=1.8, device="cuda:0",
                  batch=8, restart=25, reg=0.1, storage="f64"):
@@ -258,14 +274,7 @@ class Experiment:
         m = torch.zeros_like(p)
         v = torch.zeros_like(p)
         B, nc = self.batch, self.nc
-        order = list(seeds)
-        rng = random.Random(seed)
-        rng.shuffle(order)
-        if revisit is not None:
-            block, rounds = revisit
-            groups = [order[i:i + B] for i in range(0, len(order), B)]
-            order = [s_ for i in range(0, len(groups), block) for _ in range(rounds)
-                     for gr in groups[i:i + block] for s_ in gr]
+        order = visit_order(seeds, B, seed, revisit)
         nxt = [0]
         length = -(-horizon // seg) * seg          # steps a full visit runs
         cache = {}                                 # seed -> [truth at t = 0, 1, ...] (complete only)
