@@ -306,8 +306,10 @@ __global__ __launch_bounds__(256, PLBM_CONV_WAVES) void k_cl_conv(const u16 *__r
 // operand layout.  An x shift of the input is an offset of the node index.
 // The input rows form a ring in LDS, so each row of the block loads one new
 // input row.  Block = WG_SEG nodes x WG_ROWS rows of one frame; wave w owns
-// taps w, w+4, w+8.  The next row's global loads are issued before the
-// current row's MFMAs.
+// taps w and w+4 and the nodes 16 w .. 16 w + 15 of tap 8, whose four
+// partials are summed through LDS in a fixed order (nine MFMAs per row on
+// every wave; with all of tap 8 on wave 0 its SIMD did twelve).  The next
+// row's global loads are issued before the current row's MFMAs.
 // ---------------------------------------------------------------------------
 constexpr int WG_AN = WG_SEG + 2;               // nodes of one input row: x0 - 1 .. x0 + WG_SEG
 constexpr int WG_AVEC = WG_AN * CH / 8;         // 16-byte vectors of one input row
@@ -367,6 +369,7 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
     // a ring of three input rows: row yy sits in slot (yy - y0 + 1) % 3
     __shared__ __attribute__((aligned(16))) u16 sa[3][WG_AN][CH];
     __shared__ float bred[4][4][8];
+    __shared__ float red8[4][16][64];    // the four waves' partials of tap 8
     const int f = blockIdx.z;
     const int segs = nx / WG_SEG;
     const int x0 = (blockIdx.x % segs) * WG_SEG;
@@ -406,14 +409,16 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
                                                     (t & 3) * 8);
             wg_load_a(a, fbase, nx, ny, x0, y + 2, R.a0, R.a1);
         }
-        // A = dz^T (row o = l&31, k = nodes), B = a_t (col i = l&31, k = nodes)
+        // A = dz^T (row o = l&31, k = nodes), B = a_t (col i = l&31, k = nodes).
+        // Wave w takes taps w and w + 4 over all 64 nodes and tap 8 over
+        // nodes 16 w .. 16 w + 15 (nine MFMAs per row on every wave).
 #pragma unroll
         for (int kc = 0; kc < WG_SEG / 16; ++kc) {
             const bf16x8 av = wg_operand(sdz, kc * 16, l);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                const int tap = wv + 4 * q;
-                if (tap >= TAPS) break;
+                if (q == 2 && kc != wv) continue;
+                const int tap = q == 2 ? 8 : wv + 4 * q;
                 const int dy = tap / 3, dx = tap % 3;    // input row y + dy - 1, node x + dx - 1
                 const int slot = (r + dy) % 3;
                 // output node x0 + n reads input node x0 + n + dx - 1, LDS node n + dx
@@ -422,6 +427,8 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
             }
         }
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red8[wv][r][l] = acc[2][r];
     // bias: sum the per-thread channel sums over the 16 nodes of the wave
     // (lanes 4 n + q), then over the four waves, in a fixed order
 #pragma unroll
@@ -438,14 +445,22 @@ __global__ __launch_bounds__(256) void k_cl_wgrad(const u16 *__restrict__ a, con
     const size_t nblk = (size_t)gridDim.x * gridDim.y * gridDim.z;
     const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 2; ++q) {
         const int tap = wv + 4 * q;
-        if (tap >= TAPS) break;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int o = 8 * (r / 4) + 4 * (l >> 5) + (r & 3);
             part[blk * LAYER_W + ((size_t)tap * CH + o) * CH + (l & 31)] = acc[q][r];
         }
+    }
+    // tap 8: the four partials summed in a fixed order (red8 was written
+    // before the barrier above)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int idx = k * 256 + t, r = idx >> 6, ll = idx & 63;
+        const int o = 8 * (r / 4) + 4 * (ll >> 5) + (r & 3);
+        part[blk * LAYER_W + ((size_t)8 * CH + o) * CH + (ll & 31)] =
+            (red8[0][r][ll] + red8[1][r][ll]) + (red8[2][r][ll] + red8[3][r][ll]);
     }
     if (t < CH) {
         const int q = t >> 3, k = t & 7;
