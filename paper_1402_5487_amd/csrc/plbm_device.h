@@ -129,7 +129,7 @@ struct StF64 {
     using C = double;
     // per-node key of the stochastic rounding (unused by the other forms)
     static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
-    static constexpr bool load_prio = false;   // see StF16
+    static constexpr bool row_prio_pair = false;   // see StF16
     static __device__ __forceinline__ C dec(T h, int, const KParams &) { return h; }
     static __device__ __forceinline__ T enc(C f, int, const KParams &, uint32_t = 0) { return f; }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r64; }
@@ -140,7 +140,7 @@ struct StF32 {
     using C = float;
     // per-node key of the stochastic rounding (unused by the other forms)
     static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
-    static constexpr bool load_prio = false;   // see StF16
+    static constexpr bool row_prio_pair = false;   // see StF16
     static __device__ __forceinline__ C dec(T h, int, const KParams &) { return h; }
     static __device__ __forceinline__ T enc(C f, int, const KParams &, uint32_t = 0) { return f; }
     static __device__ __forceinline__ const SymRule<C> &R(const KParams &p) { return p.r32; }
@@ -155,9 +155,8 @@ struct StF16 {
     using C = float;
     // per-node key of the stochastic rounding (unused by the other forms)
     static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
-    // raise the wave's priority while it issues a row's loads (measured
-    // +0.5 % for the 16-bit round-to-nearest steps, a loss for the others)
-    static constexpr bool load_prio = true;
+    // an s_setprio 1 / 0 pair at the head of each row (see step_rows)
+    static constexpr bool row_prio_pair = true;
     static __device__ __forceinline__ C dec(T h, int k, const KParams &p) {
         const int c = pclass(k);
         return fmaf((float)__builtin_bit_cast(_Float16, h), p.dscale[c], p.dbase[c]);
@@ -174,7 +173,7 @@ struct StBF16 {
     using C = float;
     // per-node key of the stochastic rounding (unused by the other forms)
     static __device__ __forceinline__ uint32_t key(uint32_t node) { return node; }
-    static constexpr bool load_prio = true;    // see StF16
+    static constexpr bool row_prio_pair = true;    // see StF16
     static __device__ __forceinline__ C dec(T h, int k, const KParams &p) {
         const int c = pclass(k);
         return fmaf(__uint_as_float((uint32_t)h << 16), p.dscale[c], p.dbase[c]);
@@ -200,11 +199,10 @@ struct StBF16 {
 //  - per population: the low 24 bits of the value's bits xor the key, times
 //    a 24-bit odd constant of its own population (one full-rate 24 x 24
 //    multiply, low 32 bits kept); bits 16-31 of that product depend on all
-//    24 input bits and serve as 16 random bits (the top 13 for FP16).  An
-//    odd multiplier permutes the residues, so for a fixed value and a key
-//    uniform over the nodes the random bits are uniform: the rounding stays
-//    unbiased.  (The high half of the 48-bit product would not do: it only
-//    spans [0, multiplier / 2^8).)
+//    24 input bits and serve as the random bits.  An odd multiplier permutes
+//    the residues, so for a fixed value and a key uniform over the nodes the
+//    random bits are uniform: the rounding stays unbiased.  (The high half of
+//    the 48-bit product would not do: it only spans [0, multiplier / 2^8).)
 __device__ __forceinline__ uint32_t sr_node_key(uint32_t node)
 {
     uint32_t h = node * 0x9E3779B1u;
@@ -214,49 +212,64 @@ __device__ __forceinline__ uint32_t sr_node_key(uint32_t node)
     return h;
 }
 
-__device__ __forceinline__ uint32_t sr_bits16(uint32_t key, int k, uint32_t vbits)
+// The key as one register: left to itself the compiler keeps the last
+// xorshift's two operands apart and pays a second xor per population.
+__device__ __forceinline__ uint32_t sr_key_reg(uint32_t h)
+{
+    asm volatile("" : "+v"(h));
+    return h;
+}
+
+__device__ __forceinline__ uint32_t sr_word(uint32_t key, int k, uint32_t vbits)
 {
     // odd 24-bit multipliers, one per population (k < 25)
     const uint32_t mult = 0x9E3779u + 0x2A62D6u * (uint32_t)k | 1u;
-    // (HIP's __umul24 returns int: shift the unsigned product, not the int)
-    return (uint32_t)__umul24(vbits ^ key, mult & 0xffffffu) >> 16;
+    return (uint32_t)__umul24(vbits ^ key, mult & 0xffffffu);
 }
 
-// FP16: add 13 random bits below FP16's mantissa to the FP32 pattern, clear
-// those 13 bits, and convert (exactly, in FP16's normal range): the value
-// rounds up with probability equal to its distance from the lower FP16
-// neighbour.  Past the top of the range the sum reaches 65536 and converts
-// to infinity of v's sign (with the probability that makes the rounding
-// unbiased), so the sums still report the overflow; inf and NaN stay inf
-// and NaN (a NaN pattern cannot carry into the sign).  Below the FP16
-// normal range (|h| < 2^-14, far under the deviations this storage holds)
-// the truncated value rounds once more to the nearest subnormal.  No
-// branch: the random bits are computed for every population.
+// gfx950 converts FP32 to FP16 or BF16 with stochastic rounding in one
+// instruction (v_cvt_sr_f16_f32, v_cvt_sr_bf16_f32) that takes a 32-bit
+// random word; a probe of both over normal, subnormal, overflowing, infinite
+// and NaN inputs and 20 random words matched the following description.
+//  - BF16: the word's top 16 bits are added below BF16's kept bits of the
+//    FP32 pattern and the sum truncated; infinities and NaNs are unchanged.
+//    The value rounds up with probability frac(h / ulp).
+//  - FP16, normal range: the word's top 13 bits are added below FP16's 11
+//    kept bits, the sum truncated and converted (exact there).  Past the top
+//    of the range the sum reaches 65536 and becomes infinity of h's sign, with
+//    the probability that keeps the rounding unbiased, so the sums still
+//    report the overflow.  Below the normal range (|h| < 2^-14, a deviation
+//    under 2^-24 of the class's largest) the random bits are aligned to the
+//    subnormal step, so those values are rounded stochastically too.  NaNs
+//    stay NaN.
+typedef _Float16 plbm_f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 plbm_bf16x2 __attribute__((ext_vector_type(2)));
+
 struct StF16SR : StF16 {
-    static __device__ __forceinline__ uint32_t key(uint32_t node) { return sr_node_key(node); }
-    static constexpr bool load_prio = false;
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return sr_key_reg(sr_node_key(node)); }
+    static constexpr bool row_prio_pair = false;
     static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t key) {
         const int c = pclass(k);
         const float v = fmaf(f, p.dinv[c], p.dnbi[c]);
         const uint32_t vb = __float_as_uint(v);
-        const uint32_t t = (vb + (sr_bits16(key, k, vb) >> 3)) & ~0x1fffu;
-        return __builtin_bit_cast(uint16_t, (_Float16)__uint_as_float(t));
+        // the upper half of the destination is kept from the first operand:
+        // v's own register, which is dead after this, so no zeroing move
+        const plbm_f16x2 r =
+            __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(plbm_f16x2, vb), v, sr_word(key, k, vb), false);
+        return __builtin_bit_cast(uint16_t, r[0]);
     }
 };
 
-// BF16 keeps FP32's upper 16 bits: adding 16 random bits to the pattern and
-// truncating rounds up with probability frac(v / ulp).  inf and NaN must
-// not move (a NaN pattern near all ones could carry into the sign): their
-// random bits are masked to zero, without a branch.
 struct StBF16SR : StBF16 {
-    static __device__ __forceinline__ uint32_t key(uint32_t node) { return sr_node_key(node); }
-    static constexpr bool load_prio = false;
+    static __device__ __forceinline__ uint32_t key(uint32_t node) { return sr_key_reg(sr_node_key(node)); }
+    static constexpr bool row_prio_pair = false;
     static __device__ __forceinline__ T enc(C f, int k, const KParams &p, uint32_t key) {
         const int c = pclass(k);
         const float v = fmaf(f, p.dinv[c], p.dnbi[c]);
         const uint32_t vb = __float_as_uint(v);
-        const uint32_t finite = (vb & 0x7f800000u) != 0x7f800000u ? 0xffffu : 0u;
-        return (uint16_t)((vb + (sr_bits16(key, k, vb) & finite)) >> 16);
+        const plbm_bf16x2 r =
+            __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(plbm_bf16x2, vb), v, sr_word(key, k, vb), false);
+        return __builtin_bit_cast(uint16_t, r[0]);
     }
 };
 
@@ -642,7 +655,17 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
         const int y = y_first + r * y_step;
         if (y >= ny) break;
         typename L::Raw raw[NQ];
-        if constexpr (S::load_prio) __builtin_amdgcn_s_setprio(1);
+        // The round-to-nearest 16-bit forms put an s_setprio 1 / s_setprio 0
+        // pair around the loads.  The compiler sinks the loads (and the whole
+        // row) into the branch that stores it, past lanes beyond a ragged
+        // edge, so both land ahead of that branch and the wave's priority is
+        // not raised while the loads issue.  The pair stays for the code it
+        // leaves: it bounds the scalar code motion at the row head, and the
+        // 4096^2 step built with it ran 0.5 % faster (0.759 against 0.755 of
+        // 8 TB/s in paired runs).  Skipping the edge lanes first, so that the
+        // pair does bracket the loads, ran at 0.747-0.750; the other forms
+        // ran no faster with the pair either way.
+        if constexpr (S::row_prio_pair) __builtin_amdgcn_s_setprio(1);
         if (NV == 1 || fast) {
 #pragma unroll
             for (int j = 0; j < Q; ++j) {
@@ -688,7 +711,7 @@ __device__ __forceinline__ void step_rows(const typename S::T *__restrict__ src,
                 }
             }
         }
-        if constexpr (S::load_prio) __builtin_amdgcn_s_setprio(0);
+        if constexpr (S::row_prio_pair) __builtin_amdgcn_s_setprio(0);
         T out[NQ][NV];
 #pragma unroll
         for (int m = 0; m < NV; ++m) {
