@@ -149,9 +149,10 @@ def test_apply_vjp_and_network_backward_match_oracle(net_setup):
 
 
 class _Segment:
-    """A segment of corrected coarse steps beside restricted fine runs (64^2
-    coarse, B runs), its loss and its gradient through every step, by the
-    building-block calls or by the fused plbm_closure_rollout_vjp."""
+    """A segment of corrected coarse steps beside restricted fine runs (n^2
+    coarse, B runs on fine seeds 3 .. 3 + B - 1), its loss and its gradient
+    through every step, by the building-block calls or by the fused
+    plbm_closure_rollout_vjp."""
 
     def __init__(self, n=64, seg=4, B=2, storage="f64"):
         from paper_1402_5487_amd import closure_train as ct
@@ -161,7 +162,7 @@ class _Segment:
         ex.fit_norm()
         ex.fit_rollout_scale(range(2), steps=20)
         self.ex = ex
-        fines = [ex.fine_lattice(s) for s in (3, 4)[:B]]
+        fines = [ex.fine_lattice(s) for s in range(3, 3 + B)]
         self.coarses = [ex.coarse_lattice().init(*ex.restricted(f)) for f in fines]
         for f, c in zip(fines, self.coarses):
             f.step(4 * 5)
@@ -225,8 +226,9 @@ class _Segment:
         return g, loss
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_fused_rollout_step_matches_the_building_blocks(storage):
+@pytest.mark.parametrize("storage,n,B", [("f64", 64, 2), ("f32", 64, 2),
+                                         ("f32", 256, 8)])   # the shipped training's frames
+def test_fused_rollout_step_matches_the_building_blocks(storage, n, B):
     """plbm_closure_rollout_vjp against the sequence rollout_loss, apply_vjp,
     backward_vjp, step_vjp it fuses: the same additions in the same order,
     so the FP64 adjoints of every step agree to the last bit (1e-15 of the
@@ -234,8 +236,9 @@ def test_fused_rollout_step_matches_the_building_blocks(storage):
     differently), the FP32 parameter gradient to 1e-6 (a last-bit change of
     an FP64 cotangent can move an FP32 rounding), and the segment loss,
     summed block by block over the steps rather than step by step, to
-    1e-13."""
-    sg = _Segment(seg=3, storage=storage)
+    1e-13.  The last case is the shape the shipped training runs: 256^2
+    frames, eight of them in each launch (grid z up to 7)."""
+    sg = _Segment(n=n, seg=3, B=B, storage=storage)
     p = init_params(0, "cuda", out_gain=1.0)
     sg.forward(p)
     keep_a, keep_b = [], []
