@@ -16,7 +16,8 @@ from paper_1402_5487_amd.lattice import Lattice
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(300, 37), (256, 64), (1000, 9)]       # ragged row ends, several tiles
+SHAPES = [(300, 37), (256, 64), (1000, 9),       # ragged row ends, several tiles
+          (1024, 1024)]                          # the closure's fine lattice
 
 
 def _lat(nx, ny, storage, seed=0):
