@@ -325,20 +325,34 @@ class Experiment:
         lam = [torch.empty(nbuf, dtype=torch.float64, device=self.device) for _ in range(B)]
         tmp = [torch.empty_like(l) for l in lam]
         scale = 1.0 / (seg * B * nc * nc)
+        # the states the backward reads, for every run and step of a segment:
+        # each step writes the state before the apply into pre_all[s], one copy
+        # of all runs makes it post_all[s + 1], and the apply shifts that copy
+        # in place (two per-run clones per step before)
+        sdt = runs[0][1].f.dtype
+        pre_all = torch.empty((seg, B, nbuf), dtype=sdt, device=self.device)
+        post_all = torch.empty((seg + 1, B, nbuf), dtype=sdt, device=self.device)
+        stream = runs[0][1].stream
         hist = []
         for it in range(1, iters + 1):
-            post = [[r[1].f.clone() for r in runs]]
-            pre, truth = [], []
+            for b, r in enumerate(runs):
+                post_all[0, b].copy_(r[1].f)
+            truth = []
             for step in range(seg):
-                for r in runs:
-                    r[1].step(1)
-                pre.append([r[1].f.clone() for r in runs])
-                self.net.forward(p, [r[1].f for r in runs])
-                self.net.apply([r[1].f for r in runs], bound=float("inf"))
-                post.append([r[1].f.clone() for r in runs])
+                for b, r in enumerate(runs):
+                    _plbm.step(r[1].desc, post_all[step, b], pre_all[step, b], 1, False, stream)
+                post_all[step + 1].copy_(pre_all[step])
+                now = list(post_all[step + 1])
+                self.net.forward(p, now)
+                self.net.apply(now, bound=float("inf"))
                 truth.append([next_truth(r) for r in runs])
                 for r in runs:
                     r[2] += 1
+            for b, r in enumerate(runs):
+                r[1].f.copy_(post_all[seg, b])
+                r[1].t += seg
+            pre = [list(x) for x in pre_all]
+            post = [list(x) for x in post_all]
             # backward through the segment (one fused call per step; the
             # segment loss stays on the device until the last)
             desc = runs[0][1].desc
