@@ -554,9 +554,10 @@ int plbm_closure_backward_vjp(plbm_closure *c, const float *params, float reg, f
  * and A_(s-1) the buffer it wrote (the network's input, as given to the last
  * plbm_closure_forward), it computes what plbm_closure_rollout_loss (at
  * Q_s), plbm_closure_apply_vjp, plbm_closure_backward_vjp and plbm_step_vjp
- * compute in sequence, with the same additions in the same order, in two
- * node passes instead of six (the three in-place passes over the adjoint
- * buffers become reads of per-node moment cotangents).
+ * compute in sequence, in two node passes instead of six (the three
+ * in-place passes over the adjoint buffers become reads of per-node moment
+ * cotangents; the loss's and the apply's moment cotangents are summed per
+ * node before they are pushed, the same terms rounded in another order).
  *   coarse  : the coarse lattice's descriptor (its omega; shape, storage and
  *             velocities must be the closure's, else PLBM_EINVAL)
  *   params, reg, grads : as plbm_closure_backward_vjp; accumulate = 0 on

@@ -230,10 +230,11 @@ class _Segment:
                                          ("f32", 256, 8)])   # the shipped training's frames
 def test_fused_rollout_step_matches_the_building_blocks(storage, n, B):
     """plbm_closure_rollout_vjp against the sequence rollout_loss, apply_vjp,
-    backward_vjp, step_vjp it fuses: the same additions in the same order,
-    so the FP64 adjoints of every step agree to the last bit (1e-15 of the
-    largest value allowed for a contraction the compiler may choose
-    differently), the FP32 parameter gradient to 1e-6 (a last-bit change of
+    backward_vjp, step_vjp it fuses: the same terms (the loss's and the
+    apply's moment cotangents summed per node before the push rather than
+    pushed one after the other), so the FP64 adjoints of every step agree
+    to the last bits (1e-15 of the largest value), the FP32 parameter
+    gradient to 1e-6 (a last-bit change of
     an FP64 cotangent can move an FP32 rounding), and the segment loss,
     summed block by block over the steps rather than step by step, to
     1e-13.  The last case is the shape the shipped training runs: 256^2
