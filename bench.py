@@ -645,7 +645,7 @@ def _max_abs(got, ref):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU; the multi-GPU "
+        print("bench.py: libplbm runs on exactly one GPU; the multi-GPU "
               "(y-slab halo exchange) path is design-only, so --gpus N>1 is not "
               "measured.", file=sys.stderr)
         sys.exit(2)
